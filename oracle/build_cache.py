@@ -1,0 +1,116 @@
+"""Build the graph cache of a workload with the CPU oracle only.
+
+    python -m oracle.build_cache c1 c2s c2 [--sweep] [--expand literal]
+
+Steps (all FP64 oracle code, no GPU):
+  1. regenerate base, queries and navigating nodes from the seed (synth);
+  2. exact kNN graph (step 1 of Alg. 3, brute force);
+  3. NSSG indexing (Alg. 3): expansion, SSG pruning, reverse-neighbour
+     checking, DFS spanning from the navigating nodes;
+  4. exact ground truth of the queries (Eq. 1's G);
+  5. Alg. 1 from the nearest navigating node at the workload's pool sizes,
+     recording ids, keys, NDC and hops as the stored expected values.
+The kNN graph is kept under data/_cpu/ (not needed by GPU runs).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import synth  # noqa: E402
+from oracle import cache, core  # noqa: E402
+
+
+def log(*a):
+    print(time.strftime("%H:%M:%S"), *a, flush=True)
+
+
+def build(name: str, sweep: bool, expand: str, sweep_only: bool = False):
+    cfg = synth.CONFIGS[name]
+    t0 = time.time()
+    base = synth.base_vectors(cfg)
+    q = synth.queries(cfg, base)
+    entry = synth.entry_choice(cfg)
+    Lq, Kq = synth.query_params(cfg)
+    log(name, "data", base.shape, q.shape, f"{time.time() - t0:.1f}s")
+    meta = dict(name=name, n=cfg["n"], d=cfg["d"], R=cfg["R"], s=cfg["s"], l=cfg["l"],
+                alpha=cfg["alpha"], knn_k=cfg["knn_k"], metric=cfg["metric"], seed=cfg["seed"],
+                expand=expand, base_sha=synth.checksum(base), queries_sha=synth.checksum(q),
+                nq=int(q.shape[0]),
+                readings=dict(visited_when_added=True, order="(dist,id)", seed="nearest_entry",
+                              reverse="two_phase_reselect", zero_dist="dropped", dfs="lowest_id_first"))
+    if not sweep_only:
+        kpath = os.path.join(cache.data_root(), "_cpu", f"{name}_knn.npy")
+        if os.path.exists(kpath):
+            knn = np.load(kpath)
+            log("knn loaded", knn.shape)
+        else:
+            t = time.time()
+            knn, _ = core.knn_graph(base, cfg["knn_k"], verbose=cfg["n"] > 100_000)
+            os.makedirs(os.path.dirname(kpath), exist_ok=True)
+            np.save(kpath, knn)
+            log("knn built", f"{time.time() - t:.1f}s")
+        t = time.time()
+        res = core.nssg_build(base, knn, cfg["l"], cfg["R"], cfg["alpha"], entry, expand)
+        g = res["graph"]
+        deg = (g != core.SENT).sum(1)
+        log("nssg built", f"{time.time() - t:.1f}s", "AOD", deg.mean(), "MOD", deg.max(),
+            "dfs edges", len(res["dfs_edges"]))
+        meta.update(aod=float(deg.mean()), mod=int(deg.max()), n_dfs_edges=int(len(res["dfs_edges"])),
+                    graph_sha=synth.checksum(g), build_s=time.time() - t)
+        t = time.time()
+        Kg = max(100, cfg["K"])
+        gt_i, gt_d = core.ground_truth(base, q, Kg, cfg["metric"])
+        log("ground truth", f"{time.time() - t:.1f}s")
+        cache.save(name, dict(graph=g, entry_ids=entry, dfs_edges=res["dfs_edges"], gt_ids=gt_i,
+                              gt_d=gt_d), meta)
+    g = cache.load(name, "graph")
+    gt_i = cache.load(name, "gt_ids")
+    Ls = sorted(set(cfg.get("L_sweep", [])) | {cfg["L"]}) if sweep else [cfg["L"]]
+    rows = []
+    for L in Ls:
+        t = time.time()
+        ids, dd, ndc, hops = core.search(base, g, entry, q, cfg["K"], L, cfg["metric"])
+        el = time.time() - t
+        r10 = core.recall_at(ids, gt_i, 10) if cfg["K"] >= 10 else None
+        row = dict(L=L, recall10=r10, ndc=float(ndc.mean()), hops=float(hops.mean()),
+                   cpu_s=el, cpu_threads=os.cpu_count(), qps=q.shape[0] / el)
+        rows.append(row)
+        log(row)
+        cache.save(name, {f"oracle_L{L}_ids": ids, f"oracle_L{L}_d": dd,
+                          f"oracle_L{L}_ndc": ndc, f"oracle_L{L}_hops": hops}, {})
+    if "L_choices" in cfg:  # mixed per-query L and K
+        t = time.time()
+        Kmax = int(Kq.max())
+        ids, dd, ndc, hops = core.search(base, g, entry, q, Kmax, int(Lq.max()), cfg["metric"],
+                                         L_arr=Lq, K_arr=Kq)
+        log("mixed L/K oracle", f"{time.time() - t:.1f}s")
+        cache.save(name, {"oracle_mixed_ids": ids, "oracle_mixed_d": dd, "oracle_mixed_ndc": ndc,
+                          "oracle_mixed_hops": hops}, {})
+    op = [r["L"] for r in rows if r["recall10"] is not None and r["recall10"] >= 0.95]
+    with open(os.path.join(cache.path(name), "sweep.json"), "w") as f:
+        json.dump(dict(rows=rows, L_op=op[0] if op else None), f, indent=1)
+    log(name, "done", f"{time.time() - t0:.1f}s", "L_op", op[0] if op else None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="+")
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--sweep-only", action="store_true")
+    ap.add_argument("--expand", default="literal", choices=["literal", "hop1first"])
+    a = ap.parse_args()
+    for nm in a.names:
+        build(nm, a.sweep, a.expand, a.sweep_only)
+
+
+if __name__ == "__main__":
+    main()
