@@ -1,0 +1,133 @@
+/*
+ * ssg.h -- C ABI of libssg, batched graph search on AMD Instinct MI355X
+ * (gfx950) for the Satellite System Graph method (Fu, Wang, Cai,
+ * arXiv 1907.06146).
+ *
+ * The library runs the paper's search (Alg. 1, "Search-on-Graph") over a
+ * fixed-width navigating-SSG graph, starting every query from the navigating
+ * node nearest to it (Sec. 4.1, last paragraph), for many queries at once.
+ * The problem statement is k-nearest-neighbour search over a base set S with
+ * Euclidean distance (Sec. 2.1, 2.2); the index is the n x m neighbour matrix
+ * the paper stores graphs in (Sec. 6.2).
+ *
+ * Conventions for every entry point:
+ *  - Array pointers documented as DEVICE point to memory on the current HIP
+ *    device, allocated and owned by the caller. The library never frees,
+ *    reallocates or retains them after the call returns.
+ *  - Calls are asynchronous: they validate the arguments on the host, enqueue
+ *    kernels on `stream` (a hipStream_t; NULL = the default stream) and
+ *    return. The caller synchronises (e.g. through torch).
+ *  - Argument errors are reported synchronously with a negative status and no
+ *    work enqueued. A launch failure returns SSG_EDEVICE. The message of the
+ *    last failing call on the calling thread is returned by ssg_last_error().
+ *  - No C++ exception crosses the ABI. The library keeps no mutable global
+ *    state except the thread-local error string; it is reentrant.
+ *  - Distances are returned as squared Euclidean distance (same order as the
+ *    Euclidean distance of the paper's notation) or, for SSG_IP, as the
+ *    negative inner product. Results are sorted ascending by (dist, id).
+ */
+#ifndef SSG_H_
+#define SSG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSG_OK = 0,
+    SSG_EINVAL = -1,       /* bad argument (null pointer, size out of range) */
+    SSG_ENOMEM = -2,       /* workspace too small */
+    SSG_EDEVICE = -3,      /* HIP launch / runtime error */
+    SSG_EUNSUPPORTED = -4  /* valid but not supported (L > SSG_L_MAX, dims, dtype) */
+} ssg_status;
+
+typedef enum { SSG_L2 = 0, SSG_IP = 1 } ssg_metric;
+
+typedef enum {
+    SSG_F32 = 0,     /* IEEE binary32 vectors */
+    SSG_BF16 = 1,    /* bfloat16 vectors, FP32 accumulation */
+    SSG_FP8E4M3 = 2  /* OCP FP8 E4M3 codes times a per-dimension FP32 scale */
+} ssg_dtype;
+
+#define SSG_SENTINEL 0xFFFFFFFFu /* padding id in graph rows and in results */
+#define SSG_L_MAX 512            /* largest supported pool size */
+#define SSG_R_MAX 64             /* largest supported graph row width */
+#define SSG_K_MAX 4096           /* largest supported result count */
+
+/* Search options (ssg_search_ex). Zero-initialise, then set what you need. */
+typedef struct {
+    int32_t exact_visited;    /* 1: visited set is an exact n-bit LDS bitset
+                                 (requires n <= SSG_EXACT_VISITED_MAX_N); the
+                                 distance count then equals Alg. 1's exactly */
+    int32_t hash_log2;        /* log2 of the LDS visited-hash size; 0 = default */
+    int32_t waves_per_block;  /* wavefronts (queries) per workgroup; 0 = default */
+    int32_t* out_ndc;         /* DEVICE int32[nq] distance computations, or NULL */
+    int32_t* out_hops;        /* DEVICE int32[nq] expansions, or NULL */
+} ssg_search_opts;
+
+#define SSG_EXACT_VISITED_MAX_N 262144
+
+/*
+ * ssg_search -- Alg. 1 for nq queries, each from its nearest navigating node.
+ *
+ *   base       DEVICE, n x d row-major vectors of `dtype` (16-byte aligned).
+ *              SSG_F32: float; SSG_BF16: uint16 bfloat16 bits;
+ *              SSG_FP8E4M3: uint8 codes, value = decode(code) * dim_scale[j].
+ *   n          number of base vectors, 1 <= n < 2^31.
+ *   d          dimension; d % 4 == 0 (F32), d % 8 == 0 (BF16), d % 16 == 0 (FP8).
+ *   dim_scale  DEVICE float[d] for SSG_FP8E4M3, else NULL.
+ *   graph      DEVICE uint32 n x R; row i lists the out-neighbours of node i,
+ *              then SSG_SENTINEL padding. Ids < n, no duplicates in a row.
+ *   R          row width, 1 <= R <= SSG_R_MAX.
+ *   entry_ids  DEVICE uint32[n_entry] navigating nodes (ids < n), 1..4096.
+ *   queries    DEVICE float nq x d row-major (FP32 whatever `dtype` is).
+ *   K, L       results per query (1..SSG_K_MAX) and pool size (1..SSG_L_MAX).
+ *              K > L is allowed: slots past the final pool are padded.
+ *   out_ids    DEVICE uint32 nq x K; out_dists DEVICE float nq x K. Row q holds
+ *              the first min(K, |S|) entries of the final pool S of query q,
+ *              then SSG_SENTINEL / +inf.
+ *              With nq == 0 nothing is enqueued and queries / outputs may be NULL.
+ *   workspace  unused by this entry point (may be NULL / 0).
+ *   stream     hipStream_t to enqueue on.
+ * Returns SSG_OK or a negative ssg_status.
+ */
+int ssg_search(const void* base, int64_t n, int32_t d, int32_t dtype, const float* dim_scale,
+               const uint32_t* graph, int32_t R, const uint32_t* entry_ids, int32_t n_entry,
+               const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
+               uint32_t* out_ids, float* out_dists, void* workspace, size_t workspace_bytes,
+               void* stream);
+
+/* ssg_search with options (statistics, exact visited set, launch shape). */
+int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const float* dim_scale,
+                  const uint32_t* graph, int32_t R, const uint32_t* entry_ids, int32_t n_entry,
+                  const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
+                  uint32_t* out_ids, float* out_dists, const ssg_search_opts* opts,
+                  void* stream);
+
+/* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
+size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
+
+/*
+ * ssg_validate_graph -- host-side check of a graph's preconditions.
+ *   graph_host  HOST uint32 n x R.
+ * Checks: ids < n, each row is ids then SSG_SENTINEL only, no duplicate ids in
+ * a row, no self loops. Returns SSG_OK, or SSG_EINVAL with the first offending
+ * row named in ssg_last_error().
+ */
+int ssg_validate_graph(const uint32_t* graph_host, int64_t n, int32_t R);
+
+/* Message of the last failing call on this thread ("" if none). The pointer
+ * stays valid until the next call on the same thread. */
+const char* ssg_last_error(void);
+
+/* Library version string. */
+const char* ssg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSG_H_ */

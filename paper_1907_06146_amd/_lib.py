@@ -1,0 +1,74 @@
+"""ctypes binding of libssg (include/ssg.h). Argument marshalling only.
+
+Every step of the search runs in the HIP kernels of ``csrc/ssg_search.hip``.
+There is no CPU or PyTorch fallback: if the shared library is missing or
+cannot be loaded, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssg.so")
+
+SSG_OK, SSG_EINVAL, SSG_ENOMEM, SSG_EDEVICE, SSG_EUNSUPPORTED = 0, -1, -2, -3, -4
+SSG_L2, SSG_IP = 0, 1
+SSG_F32, SSG_BF16, SSG_FP8E4M3 = 0, 1, 2
+SENTINEL = 0xFFFFFFFF
+L_MAX, R_MAX, K_MAX = 512, 64, 4096
+
+EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_search_workspace_bytes", "ssg_validate_graph",
+           "ssg_last_error", "ssg_version")
+
+
+class SSGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libssg error {code}: {msg}")
+        self.code = code
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("exact_visited", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
+                ("out_hops", ctypes.c_void_p)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libssg.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            P, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+            L.ssg_search.argtypes = [P, i64, i32, i32, P, P, i32, P, i32, P, i64, i32, i32, i32, P,
+                                     P, P, sz, P]
+            L.ssg_search.restype = ctypes.c_int
+            L.ssg_search_ex.argtypes = [P, i64, i32, i32, P, P, i32, P, i32, P, i64, i32, i32,
+                                        i32, P, P, ctypes.POINTER(SearchOpts), P]
+            L.ssg_search_ex.restype = ctypes.c_int
+            L.ssg_search_workspace_bytes.argtypes = [i64, i64, i32, i32, i32]
+            L.ssg_search_workspace_bytes.restype = sz
+            L.ssg_validate_graph.argtypes = [P, i64, i32]
+            L.ssg_validate_graph.restype = ctypes.c_int
+            L.ssg_last_error.restype = ctypes.c_char_p
+            L.ssg_version.restype = ctypes.c_char_p
+            _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != SSG_OK:
+        raise SSGError(rc, lib().ssg_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().ssg_last_error().decode()

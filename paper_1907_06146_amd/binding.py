@@ -1,0 +1,81 @@
+"""PyTorch-facing wrapper of ``ssg_search`` (device memory and streams only).
+
+``search`` takes torch tensors that already live on the GPU, passes their raw
+pointers and the current HIP stream to the C ABI and returns torch tensors.
+All work is done by the library's kernels, asynchronously on the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.float32: _lib.SSG_F32, torch.bfloat16: _lib.SSG_BF16, torch.uint8: _lib.SSG_FP8E4M3}
+_METRICS = {"l2": _lib.SSG_L2, "ip": _lib.SSG_IP}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need_cuda(name, t, dtypes=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+
+
+def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
+           dim_scale=None, exact_visited: bool = False, stats: bool = False,
+           waves_per_block: int = 0, hash_log2: int = 0, out=None, stream=None):
+    """Alg. 1 from the nearest navigating node for every row of ``queries``.
+
+    base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
+    graph      [n, R] int32 (or uint32 bits); padding -1 (= 0xFFFFFFFF)
+    entry_ids  [s] int32 navigating nodes
+    queries    [nq, d] float32
+    Returns (ids [nq, K] int32 with -1 padding, dists [nq, K] float32) and,
+    with stats=True, also (ndc [nq] int32, hops [nq] int32).
+    """
+    _need_cuda("base", base, tuple(_DTYPES))
+    _need_cuda("graph", graph, (torch.int32, torch.uint32))
+    _need_cuda("entry_ids", entry_ids, (torch.int32, torch.uint32))
+    _need_cuda("queries", queries, (torch.float32,))
+    if base.dim() != 2 or graph.dim() != 2 or queries.dim() != 2:
+        raise ValueError("base, graph and queries must be 2-D")
+    n, d = base.shape
+    if graph.shape[0] != n:
+        raise ValueError("graph must have one row per base vector")
+    if queries.shape[1] != d:
+        raise ValueError("queries and base differ in dimension")
+    dtype = _DTYPES[base.dtype]
+    if dtype == _lib.SSG_FP8E4M3:
+        _need_cuda("dim_scale", dim_scale, (torch.float32,))
+    nq = queries.shape[0]
+    dev = base.device
+    if out is None:
+        ids = torch.empty((nq, K), dtype=torch.int32, device=dev)
+        dd = torch.empty((nq, K), dtype=torch.float32, device=dev)
+    else:
+        ids, dd = out
+    ndc = hops = None
+    if stats:
+        ndc = torch.empty(nq, dtype=torch.int32, device=dev)
+        hops = torch.empty(nq, dtype=torch.int32, device=dev)
+    opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
+                           None if ndc is None else ndc.data_ptr(),
+                           None if hops is None else hops.data_ptr())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = _lib.lib().ssg_search_ex(
+        _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,
+        _ptr(graph), graph.shape[1], _ptr(entry_ids), entry_ids.numel(), _ptr(queries), nq, K, L,
+        _METRICS[metric], _ptr(ids), _ptr(dd), ctypes.byref(opts), ctypes.c_void_p(st.cuda_stream))
+    _lib.check(rc)
+    if stats:
+        return ids, dd, ndc, hops
+    return ids, dd

@@ -1,0 +1,664 @@
+// ssg_search.hip -- gfx950 kernels for batched greedy best-first search over
+// a navigating satellite-system graph (the paper's Alg. 1, started from the
+// navigating node nearest each query, Sec. 4.1).
+//
+// Work mapping: one 64-lane wavefront owns one query from start to finish.
+// Nothing about a query is shared with another wavefront, so no cross-wave
+// synchronisation exists on the search path.
+//
+// Per-query state (all on chip):
+//   pool      the candidate pool S of at most L entries, kept sorted, held in
+//             VGPRs: entry i lives in lane i % 64, register slot i / 64.
+//             An entry is one 64-bit key  ord(dist) << 32 | id << 1 | checked,
+//             so unsigned order is the (dist, id) order and the checked flag
+//             never decides it (ids in the pool are distinct).
+//   visited   LDS open-addressing hash of node ids that always contains every
+//             id in the pool. When it is half full it is cleared and refilled
+//             from the pool. Forgetting a node that has left the pool cannot
+//             change the result: it left because its key exceeded the L-th
+//             key, which never grows afterwards, so a recomputed copy is cut
+//             again at once. Optional exact mode: an n-bit LDS bitset.
+//   stage     LDS scratch for the merge (L keys), batch ids and keys (64 each).
+//
+// One iteration (one expansion of Alg. 1):
+//   1. ballot over the pool for the first unchecked entry; mark it checked;
+//   2. lanes 0..R-1 read the neighbour row (one coalesced row read);
+//   3. each lane tests-and-inserts its id in the visited hash (LDS atomics);
+//   4. surviving ids are compacted (ballot + mbcnt) into the batch;
+//   5. G lanes per candidate gather the candidate's vector in 16-byte chunks
+//      and reduce the distance across the group with lane shuffles;
+//   6. rank-based merge: for every new key the number of smaller pool keys
+//      (ballot + popcount) and of smaller new keys gives its slot; every pool
+//      entry moves right by the number of smaller new keys; entries landing
+//      at positions >= L fall off (truncation). Positions go through LDS once.
+// The loop ends when no pool entry is unchecked; the first K keys are written.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "ssg.h"
+
+namespace {
+
+constexpr uint32_t kSent = 0xFFFFFFFFu;
+constexpr uint64_t kNoKey = ~0ull;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Monotone map of a float to uint32 (negative zero folded onto positive zero).
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+  uint32_t b = __float_as_uint(f);
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t o) {
+  uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  return __uint_as_float(b);
+}
+__device__ __forceinline__ uint64_t make_key(float dist, uint32_t id) {
+  return ((uint64_t)ord_f32(dist) << 32) | ((uint64_t)id << 1);
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)(k >> 1) & 0x7FFFFFFFu; }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  uint32_t lo = __shfl_xor((int)(uint32_t)v, m, 64);
+  uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int lane_prefix(uint64_t mask) {  // set bits below this lane
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ uint32_t hash_slot(uint32_t id, uint32_t mask) {
+  return (id * 0x9E3779B1u) >> 7 & mask;
+}
+
+// ------------------------------------------------------------------ vector types
+// A "chunk" is 16 bytes of a stored vector: 4 f32, 8 bf16 or 16 fp8 values.
+struct F32T {
+  static constexpr int kEpc = 4;
+  __device__ static __forceinline__ void decode(uint4 c, float* x) {
+    x[0] = __uint_as_float(c.x);
+    x[1] = __uint_as_float(c.y);
+    x[2] = __uint_as_float(c.z);
+    x[3] = __uint_as_float(c.w);
+  }
+};
+struct BF16T {
+  static constexpr int kEpc = 8;
+  __device__ static __forceinline__ void decode(uint4 c, float* x) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      x[2 * i] = __uint_as_float(w[i] << 16);
+      x[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+    }
+  }
+};
+// OCP FP8 E4M3 (bias 7, no infinities, S.1111.111 is NaN): exact decode by
+// bit placement for normal codes and by one multiply for subnormal codes.
+struct FP8T {
+  static constexpr int kEpc = 16;
+  __device__ static __forceinline__ float one(uint32_t b) {
+    uint32_t s = (b & 0x80u) << 24;
+    uint32_t e = (b >> 3) & 0xFu;
+    uint32_t m = b & 0x7u;
+    float v = (e == 0u) ? (float)m * 0.001953125f  // m * 2^-9
+                        : __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return __uint_as_float(__float_as_uint(v) | s);
+  }
+  __device__ static __forceinline__ void decode(uint4 c, float* x) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) x[4 * i + b] = one((w[i] >> (8 * b)) & 0xFFu);
+    }
+  }
+};
+
+struct Args {
+  const unsigned char* base;  // n x (DC * 16) bytes
+  int64_t n;
+  int32_t d;
+  int32_t dc;                 // 16-byte chunks per vector
+  const float* dim_scale;     // fp8 only
+  const uint32_t* graph;
+  int32_t R;
+  const uint32_t* entry;
+  int32_t s;
+  const float* queries;
+  int64_t nq;
+  int32_t K, L, metric;
+  uint32_t* out_ids;
+  float* out_d;
+  int32_t* out_ndc;
+  int32_t* out_hops;
+  int32_t exact;       // 1: bitset visited
+  int32_t hash_log2;   // hash mode: log2 table size
+  int32_t lds_per_wave;
+};
+
+// ------------------------------------------------------------------ kernel
+// T: stored element type; DC: chunks per vector (0 = runtime, query in LDS);
+// G: lanes cooperating on one candidate; PREG: pool registers per lane.
+template <typename T, int DC, int G, int PREG>
+__global__ __launch_bounds__(256) void search_kernel(Args a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int EPC = T::kEpc;
+  constexpr int CPP = 64 / G;                           // candidates per pass
+  constexpr int NCH = DC > 0 ? (DC + G - 1) / G : 1;    // chunks per lane
+  constexpr int LCAP = 64 * PREG;
+  constexpr bool kQueryInRegs = DC > 0;
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t qid = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  if (qid >= a.nq) return;  // uniform per wavefront
+
+  unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
+  uint64_t* stage = reinterpret_cast<uint64_t*>(my);
+  uint64_t* bkeys = stage + LCAP;
+  uint32_t* bids = reinterpret_cast<uint32_t*>(bkeys + 64);
+  float* qlds = reinterpret_cast<float*>(bids + 64);  // runtime-DC query copy
+  uint32_t* table = reinterpret_cast<uint32_t*>(qlds + (kQueryInRegs ? 0 : a.dc * EPC));
+
+  const int g = lane % G;
+  const int grp = lane / G;
+  const float* q = a.queries + (size_t)qid * a.d;
+  const bool ip = a.metric == 1;
+  const int L = a.L;
+
+  // query fragment: lane g holds chunks g, g+G, ... (EPC floats each)
+  float qf[kQueryInRegs ? NCH * EPC : 1];
+  if constexpr (kQueryInRegs) {
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const int ch = g + G * t;
+      if (DC % G == 0 || ch < DC) {
+#pragma unroll
+        for (int e = 0; e < EPC; e += 4) {
+          float4 v = *reinterpret_cast<const float4*>(q + ch * EPC + e);
+          qf[t * EPC + e] = v.x;
+          qf[t * EPC + e + 1] = v.y;
+          qf[t * EPC + e + 2] = v.z;
+          qf[t * EPC + e + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) qf[t * EPC + e] = 0.f;
+      }
+    }
+  } else {
+    for (int j = lane; j < a.d; j += 64) qlds[j] = q[j];
+  }
+  // fp8: fold the per-dimension scale into the chunk decode below
+  const float* scale = a.dim_scale;
+
+  // visited structure
+  const uint32_t hmask = (1u << a.hash_log2) - 1u;
+  const int twords = a.exact ? (int)((a.n + 31) >> 5) : (int)(hmask + 1u);
+  const uint32_t tfill = a.exact ? 0u : kSent;
+  for (int i = lane; i < twords; i += 64) table[i] = tfill;
+  wave_sync();
+  int hcount = 0;                         // ids inserted since the last clear
+  const int hlimit = (int)((hmask + 1u) >> 1);
+
+  // distance of the candidates in bids[0..m) -> bkeys[0..m)
+  auto batch_keys = [&](int m) {
+    for (int c0 = 0; c0 < m; c0 += CPP) {
+      const int c = c0 + grp;
+      const bool valid = c < m;
+      const uint32_t id = valid ? bids[c] : 0u;
+      const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)id * a.dc * 16);
+      float acc = 0.f;
+      if constexpr (kQueryInRegs) {
+        uint4 buf[NCH];
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+          const int ch = g + G * t;
+          if (valid && (DC % G == 0 || ch < DC)) buf[t] = vec[ch];
+          else buf[t] = make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+          const int ch = g + G * t;
+          if (DC % G == 0 || ch < DC) {
+            float x[EPC];
+            T::decode(buf[t], x);
+            if (scale) {
+#pragma unroll
+              for (int e = 0; e < EPC; ++e) x[e] *= scale[ch * EPC + e];
+            }
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+              if (ip) {
+                acc = fmaf(qf[t * EPC + e], x[e], acc);
+              } else {
+                const float df = qf[t * EPC + e] - x[e];
+                acc = fmaf(df, df, acc);
+              }
+            }
+          }
+        }
+      } else {
+        if (valid) {
+          for (int ch = g; ch < a.dc; ch += G) {
+            float x[EPC];
+            T::decode(vec[ch], x);
+            if (scale) {
+#pragma unroll
+              for (int e = 0; e < EPC; ++e) x[e] *= scale[ch * EPC + e];
+            }
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+              const float qv = qlds[ch * EPC + e];
+              if (ip) {
+                acc = fmaf(qv, x[e], acc);
+              } else {
+                const float df = qv - x[e];
+                acc = fmaf(df, df, acc);
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = G / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (valid && g == 0) bkeys[c] = make_key(ip ? -acc : acc, id);
+    }
+    wave_sync();
+  };
+
+  // test-and-insert id; returns true when the id was not yet visited
+  auto visit = [&](uint32_t id) -> bool {
+    if (a.exact) {
+      const uint32_t bit = 1u << (id & 31u);
+      const uint32_t old = atomicOr(&table[id >> 5], bit);
+      return (old & bit) == 0u;
+    }
+    uint32_t h = hash_slot(id, hmask);
+    for (;;) {
+      const uint32_t cur = table[h];
+      if (cur == id) return false;
+      if (cur == kSent) {
+        const uint32_t old = atomicCAS(&table[h], kSent, id);
+        if (old == kSent) return true;
+        if (old == id) return false;
+      }
+      h = (h + 1u) & hmask;
+    }
+  };
+
+  uint64_t pool[PREG];
+#pragma unroll
+  for (int k = 0; k < PREG; ++k) pool[k] = kNoKey;
+  int size = 0;
+  int ndc = 0, hops = 0;
+
+  // ---- entry: the nearest navigating node seeds the pool
+  {
+    uint64_t best = kNoKey;
+    for (int e0 = 0; e0 < a.s; e0 += 64) {
+      const int m = min(64, a.s - e0);
+      if (lane < m) bids[lane] = a.entry[e0 + lane];
+      wave_sync();
+      batch_keys(m);
+      if (lane < m) best = min(best, bkeys[lane]);
+      wave_sync();
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) best = min(best, shfl_xor64(best, off));
+    ndc = a.s;
+    if (lane == 0) pool[0] = best;
+    size = 1;
+    if (lane == 0) visit(key_id(best));
+    hcount = 1;
+    wave_sync();
+  }
+
+  for (;;) {
+    // 1. first unchecked entry
+    int pos = -1;
+    uint32_t p = 0;
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) {
+      if (pos < 0) {
+        const uint64_t um = __ballot((pool[k] & 1ull) == 0ull);
+        if (um) {
+          const int l = __builtin_ctzll(um);
+          pos = k * 64 + l;
+          p = key_id(readlane64(pool[k], l));
+          if (lane == l) pool[k] |= 1ull;
+        }
+      }
+    }
+    if (pos < 0) break;
+    ++hops;
+    if (hops > a.n + 1) break;  // cannot happen (each node is expanded at most once); bounds the loop
+
+    // visited table maintenance: rebuild from the pool when half full
+    if (!a.exact && hcount + a.R > hlimit) {
+      for (int i = lane; i <= (int)hmask; i += 64) table[i] = kSent;
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < PREG; ++k)
+        if (pool[k] != kNoKey) visit(key_id(pool[k]));
+      wave_sync();
+      hcount = size;
+    }
+
+    // 2-4. neighbour row, visited filter, compaction
+    const uint32_t nb = lane < a.R ? a.graph[(size_t)p * a.R + lane] : kSent;
+    const bool fresh = nb != kSent && visit(nb);
+    const uint64_t fm = __ballot(fresh);
+    const int m = __popcll(fm);
+    if (fresh) bids[lane_prefix(fm)] = nb;
+    wave_sync();
+    if (m == 0) continue;
+    hcount += m;
+    ndc += m;
+
+    // 5. distances
+    batch_keys(m);
+
+    // 6. rank-based merge of the m new keys into the pool, truncated to L
+    const uint64_t b = lane < m ? bkeys[lane] : kNoKey;
+    int rank = 0, qcnt = 0;
+    int shift[PREG];
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) shift[k] = 0;
+    for (int j = 0; j < m; ++j) {
+      const uint64_t bj = readlane64(b, j);
+      int r = 0;
+#pragma unroll
+      for (int k = 0; k < PREG; ++k) {
+        r += __popcll(__ballot(pool[k] < bj));
+        shift[k] += bj < pool[k] ? 1 : 0;
+      }
+      if (lane == j) rank = r;
+      qcnt += bj < b ? 1 : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) {
+      const int np = k * 64 + lane + shift[k];
+      if (pool[k] != kNoKey && np < L) stage[np] = pool[k];
+    }
+    if (lane < m && rank + qcnt < L) stage[rank + qcnt] = b;
+    wave_sync();
+    size = min(L, size + m);
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) {
+      const int i = k * 64 + lane;
+      pool[k] = i < size ? stage[i] : kNoKey;
+    }
+    wave_sync();
+  }
+
+  // ---- output: first K pool entries, padded
+  uint32_t* oid = a.out_ids + (size_t)qid * a.K;
+  float* od = a.out_d + (size_t)qid * a.K;
+#pragma unroll
+  for (int k = 0; k < PREG; ++k) {
+    const int i = k * 64 + lane;
+    if (i < a.K) {
+      const uint64_t key = pool[k];
+      oid[i] = key == kNoKey ? kSent : key_id(key);
+      od[i] = key == kNoKey ? __uint_as_float(0x7F800000u) : unord_f32((uint32_t)(key >> 32));
+    }
+  }
+  for (int i = LCAP + lane; i < a.K; i += 64) {
+    oid[i] = kSent;
+    od[i] = __uint_as_float(0x7F800000u);
+  }
+  if (lane == 0) {
+    if (a.out_ndc) a.out_ndc[qid] = ndc;
+    if (a.out_hops) a.out_hops[qid] = hops;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+using KernelFn = void (*)(Args);
+
+struct Launch {
+  KernelFn fn = nullptr;
+  int preg = 0;
+  bool query_in_regs = false;
+};
+
+template <typename T, int DC, int G>
+KernelFn pick_preg(int preg) {
+  switch (preg) {
+    case 1: return search_kernel<T, DC, G, 1>;
+    case 2: return search_kernel<T, DC, G, 2>;
+    case 4: return search_kernel<T, DC, G, 4>;
+    default: return search_kernel<T, DC, G, 8>;
+  }
+}
+
+// Launch tables: compile-time chunk counts for the dimensions of the paper's
+// datasets (Table 2: 96, 100, 128, 300, 960) and of the tiny workload (32).
+// G is chosen so each lane keeps at most 32 query floats in registers; other
+// shapes use the runtime-chunk kernel (DC = 0) with the query in LDS.
+template <typename T>
+struct Table;
+template <>
+struct Table<F32T> {
+  static Launch pick(int dc, int preg) {
+    Launch l{nullptr, preg, true};
+    switch (dc) {
+      case 8: l.fn = pick_preg<F32T, 8, 2>(preg); return l;     // d = 32
+      case 24: l.fn = pick_preg<F32T, 24, 8>(preg); return l;   // d = 96
+      case 25: l.fn = pick_preg<F32T, 25, 8>(preg); return l;   // d = 100
+      case 32: l.fn = pick_preg<F32T, 32, 8>(preg); return l;   // d = 128
+      case 75: l.fn = pick_preg<F32T, 75, 16>(preg); return l;  // d = 300
+      default: break;
+    }
+    l.query_in_regs = false;
+    l.fn = pick_preg<F32T, 0, 16>(preg);
+    return l;
+  }
+};
+template <>
+struct Table<BF16T> {
+  static Launch pick(int dc, int preg) {
+    Launch l{nullptr, preg, true};
+    switch (dc) {
+      case 12: l.fn = pick_preg<BF16T, 12, 4>(preg); return l;  // d = 96
+      case 16: l.fn = pick_preg<BF16T, 16, 4>(preg); return l;  // d = 128
+      default: break;
+    }
+    l.query_in_regs = false;
+    l.fn = pick_preg<BF16T, 0, 16>(preg);
+    return l;
+  }
+};
+template <>
+struct Table<FP8T> {
+  static Launch pick(int dc, int preg) {
+    Launch l{nullptr, preg, true};
+    switch (dc) {
+      case 6: l.fn = pick_preg<FP8T, 6, 4>(preg); return l;  // d = 96
+      case 8: l.fn = pick_preg<FP8T, 8, 4>(preg); return l;  // d = 128
+      default: break;
+    }
+    l.query_in_regs = false;
+    l.fn = pick_preg<FP8T, 0, 16>(preg);
+    return l;
+  }
+};
+
+int check_common(const void* base, int64_t n, int32_t d, int32_t dtype, const float* dim_scale,
+                 const uint32_t* graph, int32_t R, const uint32_t* entry_ids, int32_t n_entry,
+                 const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
+                 uint32_t* out_ids, float* out_dists) {
+  if (nq < 0) return fail(SSG_EINVAL, "nq must be >= 0 (got %lld)", (long long)nq);
+  if (n < 1 || n >= (int64_t)0x7FFFFFFF) return fail(SSG_EINVAL, "n must be in [1, 2^31-1) (got %lld)", (long long)n);
+  if (d < 1) return fail(SSG_EINVAL, "d must be >= 1 (got %d)", d);
+  if (R < 1) return fail(SSG_EINVAL, "R must be >= 1 (got %d)", R);
+  if (n_entry < 1 || n_entry > 4096) return fail(SSG_EINVAL, "n_entry must be in [1, 4096] (got %d)", n_entry);
+  if (K < 1) return fail(SSG_EINVAL, "K must be >= 1 (got %d)", K);
+  if (L < 1) return fail(SSG_EINVAL, "L must be >= 1 (got %d)", L);
+  if (metric != SSG_L2 && metric != SSG_IP) return fail(SSG_EINVAL, "unknown metric %d", metric);
+  if (dtype != SSG_F32 && dtype != SSG_BF16 && dtype != SSG_FP8E4M3)
+    return fail(SSG_EINVAL, "unknown dtype %d", dtype);
+  if (!base || !graph || !entry_ids || (nq > 0 && (!queries || !out_ids || !out_dists)))
+    return fail(SSG_EINVAL, "required pointer is NULL");
+  if (dtype == SSG_FP8E4M3 && !dim_scale) return fail(SSG_EINVAL, "FP8 vectors need dim_scale");
+  if (reinterpret_cast<uintptr_t>(base) % 16 || reinterpret_cast<uintptr_t>(queries) % 16)
+    return fail(SSG_EINVAL, "base and queries must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(graph) % 4 || reinterpret_cast<uintptr_t>(entry_ids) % 4)
+    return fail(SSG_EINVAL, "graph and entry_ids must be 4-byte aligned");
+  const int epc = dtype == SSG_F32 ? 4 : dtype == SSG_BF16 ? 8 : 16;
+  if (d % epc) return fail(SSG_EUNSUPPORTED, "d=%d must be a multiple of %d for this dtype", d, epc);
+  if (d % 4) return fail(SSG_EUNSUPPORTED, "d must be a multiple of 4");
+  if (R > SSG_R_MAX) return fail(SSG_EUNSUPPORTED, "R=%d exceeds %d", R, SSG_R_MAX);
+  if (L > SSG_L_MAX) return fail(SSG_EUNSUPPORTED, "L=%d exceeds %d", L, SSG_L_MAX);
+  if (K > SSG_K_MAX) return fail(SSG_EUNSUPPORTED, "K=%d exceeds %d", K, SSG_K_MAX);
+  return SSG_OK;
+}
+
+int preg_for(int L) { return L <= 64 ? 1 : L <= 128 ? 2 : L <= 256 ? 4 : 8; }
+
+}  // namespace
+
+extern "C" {
+
+const char* ssg_last_error(void) { return g_err.c_str(); }
+
+const char* ssg_version(void) { return "libssg 0.1 gfx950"; }
+
+size_t ssg_search_workspace_bytes(int64_t, int64_t, int32_t, int32_t, int32_t) { return 0; }
+
+int ssg_validate_graph(const uint32_t* graph, int64_t n, int32_t R) {
+  if (!graph || n < 1 || R < 1) return fail(SSG_EINVAL, "bad graph arguments");
+  std::string seen;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t* row = graph + (size_t)i * R;
+    bool tail = false;
+    for (int t = 0; t < R; ++t) {
+      const uint32_t v = row[t];
+      if (v == kSent) { tail = true; continue; }
+      if (tail) return fail(SSG_EINVAL, "row %lld: id after padding at slot %d", (long long)i, t);
+      if (v >= (uint64_t)n) return fail(SSG_EINVAL, "row %lld: id %u >= n", (long long)i, v);
+      if (v == (uint64_t)i) return fail(SSG_EINVAL, "row %lld: self loop", (long long)i);
+      for (int u = 0; u < t; ++u)
+        if (row[u] == v) return fail(SSG_EINVAL, "row %lld: duplicate id %u", (long long)i, v);
+    }
+  }
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const float* dim_scale,
+                  const uint32_t* graph, int32_t R, const uint32_t* entry_ids, int32_t n_entry,
+                  const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
+                  uint32_t* out_ids, float* out_dists, const ssg_search_opts* opts,
+                  void* stream) {
+  int rc = check_common(base, n, d, dtype, dim_scale, graph, R, entry_ids, n_entry, queries, nq, K,
+                        L, metric, out_ids, out_dists);
+  if (rc) return rc;
+  ssg_search_opts o{};
+  if (opts) o = *opts;
+  if (nq == 0) { g_err.clear(); return SSG_OK; }
+  const int preg = preg_for(L);
+  const int epc = dtype == SSG_F32 ? 4 : dtype == SSG_BF16 ? 8 : 16;
+  const int dc = d / epc;
+  Launch lc = dtype == SSG_F32    ? Table<F32T>::pick(dc, preg)
+              : dtype == SSG_BF16 ? Table<BF16T>::pick(dc, preg)
+                                  : Table<FP8T>::pick(dc, preg);
+  int wpb = o.waves_per_block > 0 ? o.waves_per_block : 4;
+  if (wpb > 4) return fail(SSG_EINVAL, "waves_per_block must be in [1, 4]");
+  Args a{};
+  a.base = static_cast<const unsigned char*>(base);
+  a.n = n;
+  a.d = d;
+  a.dc = dc;
+  a.dim_scale = dtype == SSG_FP8E4M3 ? dim_scale : nullptr;
+  a.graph = graph;
+  a.R = R;
+  a.entry = entry_ids;
+  a.s = n_entry;
+  a.queries = queries;
+  a.nq = nq;
+  a.K = K;
+  a.L = L;
+  a.metric = metric;
+  a.out_ids = out_ids;
+  a.out_d = out_dists;
+  a.out_ndc = o.out_ndc;
+  a.out_hops = o.out_hops;
+  a.exact = o.exact_visited ? 1 : 0;
+  const int lcap = 64 * preg;
+  size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 + (lc.query_in_regs ? 0 : (size_t)d * 4);
+  size_t table;
+  if (a.exact) {
+    if (n > SSG_EXACT_VISITED_MAX_N)
+      return fail(SSG_EUNSUPPORTED, "exact visited set needs n <= %d", SSG_EXACT_VISITED_MAX_N);
+    table = (size_t)((n + 31) / 32) * 4;
+    a.hash_log2 = 0;
+  } else {
+    int hl = o.hash_log2 > 0 ? o.hash_log2 : 11;
+    // the table must hold the pool plus one row at load <= 1/2
+    while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
+    if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");
+    a.hash_log2 = hl;
+    table = (size_t)4 << hl;
+  }
+  size_t per_wave = (fixed + table + 15) & ~(size_t)15;
+  if (per_wave * wpb > 64 * 1024) {
+    wpb = (int)((64 * 1024) / per_wave);
+    if (wpb < 1) return fail(SSG_EUNSUPPORTED, "per-query LDS need %zu exceeds the CU", per_wave);
+  }
+  a.lds_per_wave = (int)per_wave;
+  const size_t lds = per_wave * wpb;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t blocks = (nq + wpb - 1) / wpb;
+  if (blocks > 0x7FFFFFFF) return fail(SSG_EINVAL, "too many queries");
+  hipLaunchKernelGGL(lc.fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_search(const void* base, int64_t n, int32_t d, int32_t dtype, const float* dim_scale,
+               const uint32_t* graph, int32_t R, const uint32_t* entry_ids, int32_t n_entry,
+               const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
+               uint32_t* out_ids, float* out_dists, void* workspace, size_t workspace_bytes,
+               void* stream) {
+  (void)workspace;
+  (void)workspace_bytes;
+  return ssg_search_ex(base, n, d, dtype, dim_scale, graph, R, entry_ids, n_entry, queries, nq, K,
+                       L, metric, out_ids, out_dists, nullptr, stream);
+}
+
+}  // extern "C"

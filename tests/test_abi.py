@@ -1,0 +1,105 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1907_06146_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ssg.h")).read()
+    return sorted(set(re.findall(r"\b(ssg_[a-z_]+)\s*\(", txt)) - {"ssg_search_opts"})
+
+
+def test_header_and_binding_agree():
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_library_exports_every_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.ssg_version().decode().startswith("libssg")
+    assert L.ssg_search_workspace_bytes(10, 10, 10, 10, 0) == 0
+
+
+def _fake(n_bytes=1 << 12):
+    buf = np.zeros(n_bytes, np.uint8)
+    addr = buf.ctypes.data
+    addr = (addr + 255) & ~255
+    return buf, addr
+
+
+BASE = dict(n=100, d=32, dtype=0, R=8, n_entry=2, nq=4, K=10, L=20, metric=0)
+
+
+def _call(**kw):
+    a = dict(BASE)
+    a.update(kw)
+    keep, p = _fake()
+    ptr = kw.get("ptr", p)
+    return _lib.lib().ssg_search(ptr, a["n"], a["d"], a["dtype"], None, ptr, a["R"], ptr,
+                                 a["n_entry"], ptr, a["nq"], a["K"], a["L"], a["metric"], ptr,
+                                 ptr, None, 0, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(K=0), _lib.SSG_EINVAL),
+    (dict(L=0), _lib.SSG_EINVAL),
+    (dict(d=0), _lib.SSG_EINVAL),
+    (dict(R=0), _lib.SSG_EINVAL),
+    (dict(n_entry=0), _lib.SSG_EINVAL),
+    (dict(nq=-1), _lib.SSG_EINVAL),
+    (dict(n=0), _lib.SSG_EINVAL),
+    (dict(n=2 ** 31), _lib.SSG_EINVAL),
+    (dict(metric=7), _lib.SSG_EINVAL),
+    (dict(dtype=9), _lib.SSG_EINVAL),
+    (dict(dtype=2), _lib.SSG_EINVAL),  # FP8 without a scale vector
+    (dict(ptr=None), _lib.SSG_EINVAL),
+    (dict(L=513), _lib.SSG_EUNSUPPORTED),
+    (dict(R=65), _lib.SSG_EUNSUPPORTED),
+    (dict(K=5000), _lib.SSG_EUNSUPPORTED),
+    (dict(d=30), _lib.SSG_EUNSUPPORTED),
+    (dict(dtype=1, d=36), _lib.SSG_EUNSUPPORTED),
+])
+def test_argument_errors(kw, code):
+    assert _call(**kw) == code
+    assert len(_lib.last_error()) > 0
+
+
+def test_misaligned_base_is_rejected():
+    keep, p = _fake()
+    L = _lib.lib()
+    rc = L.ssg_search(p + 4, 100, 32, 0, None, p, 8, p, 2, p, 4, 10, 20, 0, p, p, None, 0, None)
+    assert rc == _lib.SSG_EINVAL and "aligned" in _lib.last_error()
+
+
+def _validate(g):
+    g = np.ascontiguousarray(g, np.uint32)
+    return _lib.lib().ssg_validate_graph(g.ctypes.data_as(ctypes.c_void_p), g.shape[0], g.shape[1])
+
+
+def test_validate_graph():
+    S = 0xFFFFFFFF
+    assert _validate([[1, 2, S], [0, S, S], [0, 1, S]]) == 0
+    assert _validate([[1, S, 2], [0, S, S], [0, 1, S]]) == _lib.SSG_EINVAL  # id after padding
+    assert "row 0" in _lib.last_error()
+    assert _validate([[1, 1, S], [0, S, S], [0, 1, S]]) == _lib.SSG_EINVAL  # duplicate
+    assert _validate([[0, S, S], [0, S, S], [0, 1, S]]) == _lib.SSG_EINVAL  # self loop
+    assert _validate([[1, 3, S], [0, S, S], [0, 1, S]]) == _lib.SSG_EINVAL  # id >= n
+
+
+def test_validate_cached_graphs():
+    from oracle import cache
+    for name in ("c1", "c2s"):
+        if not cache.exists(name, "graph"):
+            pytest.skip("graph cache not built")
+        g = cache.load(name, "graph")
+        assert _validate(g) == 0

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP search against the CPU oracle, through the C ABI.
+
+Bar (FP32): the oracle's id list for >= 99.9 % of queries; every other query
+explained by distance ties (FP64 keys of both lists agree within 1e-5
+relative, element by element); recall@K within 0.001 of the oracle's. On
+integer-valued data (the SIFT-shaped workloads) FP32 sums are exact, so ids
+and distances must match exactly. With the exact visited set the distance
+count (NDC) and the expansion count (hops) must equal the oracle's.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cache, core
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+SENT = core.SENT
+
+
+def _dev(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+def _gpu(base, g, entry, q, K, L, metric="l2", **kw):
+    from paper_1907_06146_amd import search
+    out = search(_dev(base), _dev(g), _dev(entry), _dev(q), K, L, metric, stats=True, **kw)
+    torch.cuda.synchronize()
+    ids, dd, ndc, hops = (t.cpu().numpy() for t in out)
+    return ids.view(np.uint32), dd, ndc, hops
+
+
+def _compare(base, q, gi, gd, oi, od, metric="l2", tol=1e-5, min_match=0.999):
+    """Row-wise id equality, mismatches explained by ties (FP64 keys)."""
+    same = (gi == oi).all(1)
+    bad = np.nonzero(~same)[0]
+    if len(bad):
+        kg = core.pair_keys(base, q[bad], gi[bad], metric)
+        ko = core.pair_keys(base, q[bad], oi[bad], metric)
+        fin = np.isfinite(ko) & np.isfinite(kg)
+        assert (np.isfinite(ko) == np.isfinite(kg)).all(), "padding differs"
+        rel = np.abs(kg[fin] - ko[fin]) / np.maximum(np.abs(ko[fin]), 1e-30)
+        assert (rel <= tol).all(), f"unexplained mismatch: max rel {rel.max()}"
+    # at most 0.1 % of rows (and at least one row) may differ, all explained above
+    allowed = max(1, int((1.0 - min_match) * len(same)))
+    assert (~same).sum() <= allowed, f"only {same.mean():.4f} of rows match"
+    # GPU distances are the FP32 evaluation of the oracle's FP64 keys
+    fin = np.isfinite(od)
+    assert (np.isfinite(gd) == fin).all()
+    err = np.abs(gd[fin] - od[fin]) / np.maximum(np.abs(od[fin]), 1e-6)
+    return same.mean(), float(err.max()) if err.size else 0.0
+
+
+@pytest.fixture(scope="module")
+def c2s():
+    cfg = synth.CONFIGS["c2s"]
+    base = synth.base_vectors(cfg)
+    q = synth.queries(cfg, base)
+    entry = synth.entry_choice(cfg)
+    knn, _ = core.knn_graph(base, cfg["knn_k"])
+    g = core.nssg_build(base, knn, cfg["l"], cfg["R"], cfg["alpha"], entry)["graph"]
+    return base, q, g, entry
+
+
+@pytest.mark.parametrize("L,K", [(1, 1), (10, 10), (64, 100), (100, 10), (128, 128), (129, 50),
+                                 (256, 100), (300, 300), (512, 100)])
+def test_integer_data_bit_exact(c2s, L, K):
+    base, q, g, entry = c2s
+    oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
+    for exact in (True, False):
+        gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=exact)
+        assert np.array_equal(gi, oi)
+        assert np.array_equal(gd.astype(np.float64), od)
+        assert np.array_equal(ghops, ohops)
+        if exact:
+            assert np.array_equal(gndc, ondc)
+        else:
+            assert (gndc >= ondc).all()
+
+
+def test_hash_rebuilds_are_result_neutral(c2s):
+    base, q, g, entry = c2s
+    K, L = 100, 256
+    oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, hash_log2=10)  # smallest table
+    assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od)
+    assert (gndc > ondc).any()  # the table was rebuilt and nodes were recomputed
+
+
+def test_bf16_storage_is_lossless_on_integer_data(c2s):
+    base, q, g, entry = c2s
+    K, L = 100, 64
+    oi, od, _, _ = core.search(base, g, entry, q, K, L)
+    from paper_1907_06146_amd import search
+    tb = torch.from_numpy(base).cuda().to(torch.bfloat16)
+    assert torch.equal(tb.float().cpu(), torch.from_numpy(base))
+    ids, dd = search(tb, _dev(g), _dev(entry), _dev(q), K, L)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(dd.cpu().numpy().astype(np.float64), od)
+
+
+def test_c1_float_data(c1_graph):
+    base, q, g, entry, gt_i, _ = c1_graph
+    K, L = 10, 50
+    oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=True)
+    frac, err = _compare(base, q, gi, gd, oi, od)
+    assert err < 1e-5
+    assert abs(core.recall_at(gi, gt_i, 10) - core.recall_at(oi, gt_i, 10)) <= 0.001
+    same = (gi == oi).all(1)
+    assert np.array_equal(gndc[same], ondc[same]) and np.array_equal(ghops[same], ohops[same])
+
+
+@pytest.mark.parametrize("L", [1, 16, 50, 200, 512])
+def test_c1_pool_sizes_and_large_k(c1_graph, L):
+    base, q, g, entry, _, _ = c1_graph
+    K = 600  # more results than the pool holds: padded
+    oi, od, _, _ = core.search(base, g, entry, q, K, L)
+    gi, gd, _, _ = _gpu(base, g, entry, q, K, L)
+    # lists up to 512 long on float data: near-equal keys deep in the list may
+    # swap between FP32 and FP64; every differing row must still be explained
+    _compare(base, q, gi, gd, oi, od, min_match=0.999 if L <= 50 else 0.9)
+    assert (gi[:, L:] == SENT).all() and np.isinf(gd[:, L:]).all()
+
+
+def test_inner_product_unit_norm():
+    cfg = synth.CONFIGS["c4s"]
+    base = synth.base_vectors(cfg)
+    q = synth.queries(cfg, base)[:500]
+    entry = synth.entry_choice(cfg)
+    knn, _ = core.knn_graph(base, cfg["knn_k"])
+    g = core.nssg_build(base, knn, cfg["l"], cfg["R"], cfg["alpha"], entry)["graph"]
+    for L, K in [(16, 1), (128, 10), (512, 100)]:
+        oi, od, _, _ = core.search(base, g, entry, q, K, L, "ip")
+        gi, gd, _, _ = _gpu(base, g, entry, q, K, L, "ip")
+        _compare(base, q, gi, gd, oi, od, "ip")
+
+
+def test_row_permutation_and_determinism(c2s):
+    base, q, g, entry = c2s
+    rng = np.random.default_rng(5)
+    gp = g.copy()
+    for i in range(len(gp)):
+        k = int((gp[i] != SENT).sum())
+        gp[i, :k] = rng.permutation(gp[i, :k])
+    a = _gpu(base, g, entry, q, 50, 96)
+    b = _gpu(base, gp, entry, q, 50, 96)
+    c = _gpu(base, g, entry, q, 50, 96)
+    for x, y, z in zip(a[:2], b[:2], c[:2]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(9)
+    base = rng.integers(0, 50, size=(500, 32)).astype(np.float32)
+    # graph with isolated nodes and empty rows
+    g = np.full((500, 8), SENT, np.uint32)
+    for i in range(0, 500, 2):
+        nb = rng.choice(np.delete(np.arange(500), i), size=int(rng.integers(0, 9)), replace=False)
+        g[i, :len(nb)] = nb
+    q = rng.integers(0, 50, size=(70, 32)).astype(np.float32)
+    for entry in (np.array([1], np.uint32), np.arange(0, 500, 7, dtype=np.uint32)):
+        for K, L in [(1, 1), (5, 3), (64, 64), (100, 65)]:
+            oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
+            gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=True)
+            assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od)
+            assert np.array_equal(gndc, ondc) and np.array_equal(ghops, ohops)
+    # no queries
+    from paper_1907_06146_amd import search
+    ids, dd = search(_dev(base), _dev(g), _dev(np.array([0], np.uint32)),
+                     torch.empty((0, 32), device="cuda"), 5, 5)
+    torch.cuda.synchronize()
+    assert ids.shape == (0, 5)
+
+
+def _c2_cache():
+    meta = cache.load_meta("c2")
+    if meta is None or not cache.exists("c2", "graph"):
+        pytest.skip("1M x 128 graph cache not built")
+    return meta
+
+
+def test_c2_full_size_against_stored_oracle():
+    """Full SIFT-shaped workload (1M x 128, 10,000 queries) in the launch shape
+    the benchmark times, against the oracle's stored results at the operating
+    pool size. Integer data: ids and distances must match exactly."""
+    import json
+    meta = _c2_cache()
+    with open(os.path.join(cache.path("c2"), "sweep.json")) as f:
+        sw = json.load(f)
+    L = sw["L_op"] or synth.CONFIGS["c2"]["L"]
+    if not cache.exists("c2", f"oracle_L{L}_ids"):
+        pytest.skip("no stored oracle result at the operating point")
+    cfg = synth.CONFIGS["c2"]
+    base = synth.base_vectors(cfg)
+    assert synth.checksum(base) == meta["base_sha"]
+    q = synth.queries(cfg, base)
+    g = cache.load("c2", "graph")
+    entry = cache.load("c2", "entry_ids")
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, cfg["K"], L)
+    oi = cache.load("c2", f"oracle_L{L}_ids")
+    od = cache.load("c2", f"oracle_L{L}_d")
+    oh = cache.load("c2", f"oracle_L{L}_hops")
+    assert np.array_equal(gi, oi)
+    assert np.array_equal(gd.astype(np.float64), od)
+    assert np.array_equal(ghops, oh)
+    gt = cache.load("c2", "gt_ids")
+    assert core.recall_at(gi, gt, 10) >= 0.95
