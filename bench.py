@@ -1,0 +1,205 @@
+"""Benchmark: batched Alg. 1 search on the SIFT-shaped workload, one GPU.
+
+Workload: base 1,000,000 x 128 (integers 0..255 stored as fp32), NSSG graph
+R = 50 built by the CPU oracle, 10,000 unindexed queries, K = 100, pool L =
+the smallest swept L whose oracle recall@10 is >= 0.95. One step = one
+ssg_search call over all 10,000 queries (every step of the hot path: entry
+selection, expansions, gathers, distances, merges, output). Inputs are
+resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = "c2"
+
+
+def log(*a):
+    print(f"[bench {time.strftime('%H:%M:%S')}]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha1()
+    with open(os.path.join(ROOT, "paper_1907_06146_amd", "csrc", "ssg_search.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def recall_at(ids: np.ndarray, gt: np.ndarray, k: int) -> float:
+    """Eq. 1: |R n G| / |G| with R, G the first k ids, averaged over queries."""
+    a = ids[:, :k].astype(np.int64)
+    b = gt[:, :k].astype(np.int64)
+    hit = sum(len(np.intersect1d(x[x >= 0], y)) for x, y in zip(a, b))
+    return hit / float(b.size)
+
+
+def algorithmic_bytes(ndc, hops, d, R, s, K, elem=4):
+    """Bytes Alg. 1 itself must move per query: the query, the s entry
+    vectors, one fixed-width neighbour row (R ids) per expansion, one vector
+    per further distance computation, and the K (id, dist) outputs."""
+    ndc = np.asarray(ndc, np.float64)
+    hops = np.asarray(hops, np.float64)
+    return 4 * d + s * d * elem + hops * 4 * R + (ndc - s) * d * elem + 8 * K
+
+
+def traffic_from_profile(kernel_tag: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        c = json.load(f)
+    if c.get("source_digest") != source_digest():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=0, help="pool size (default: operating point)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the CPU baseline")
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--hash-log2", type=int, default=0)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {a.gpus}); the index and every query "
+              "fit one MI355X, and no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1907_06146_amd import graph_io, search
+
+    cfg = synth.CONFIGS[WORKLOAD]
+    t0 = time.time()
+    gc = graph_io.load(WORKLOAD)
+    meta = gc["meta"]
+    base = synth.base_vectors(cfg)
+    if synth.checksum(base) != meta["base_sha"]:
+        raise SystemExit("regenerated base vectors do not match the graph cache")
+    q = synth.queries(cfg, base)
+    droot = os.path.join(graph_io.default_root(), WORKLOAD)
+    with open(os.path.join(droot, "sweep.json")) as f:
+        sweep = json.load(f)
+    L = a.L or sweep["L_op"]
+    K = cfg["K"]
+    gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
+    ondc = np.load(os.path.join(droot, f"oracle_L{L}_ndc.npy"), allow_pickle=False)
+    ohops = np.load(os.path.join(droot, f"oracle_L{L}_hops.npy"), allow_pickle=False)
+    log(f"data ready in {time.time() - t0:.1f}s: n={base.shape[0]} d={base.shape[1]} nq={len(q)} "
+        f"R={gc['graph'].shape[1]} L={L} K={K}")
+
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    tq = torch.from_numpy(q).to(dev)
+    ids = torch.empty((len(q), K), dtype=torch.int32, device=dev)
+    dd = torch.empty((len(q), K), dtype=torch.float32, device=dev)
+    kw = dict(out=(ids, dd), waves_per_block=a.waves_per_block, hash_log2=a.hash_log2)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(a.warmup):
+        search(tb, tg, te, tq, K, L, **kw)
+    torch.cuda.synchronize()
+    gids = ids.cpu().numpy()
+    r10 = recall_at(gids, gt, 10)
+    _, _, gndc, ghops = search(tb, tg, te, tq, K, L, stats=True, waves_per_block=a.waves_per_block,
+                               hash_log2=a.hash_log2)
+    gndc = gndc.cpu().numpy()
+    log(f"warmup done; GPU recall@10 = {r10:.4f}; GPU NDC {gndc.mean():.1f} "
+        f"(oracle {np.mean(ondc):.1f})")
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        search(tb, tg, te, tq, K, L, **kw)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    launch_ms = gpu_ms / a.steps
+    qps = len(q) * a.steps / (gpu_ms / 1e3)
+    log(f"{a.steps} steps: {gpu_ms:.3f} ms GPU ({launch_ms:.4f} ms/launch), wall {wall * 1e3:.1f} ms")
+
+    bq = algorithmic_bytes(ondc, ohops, base.shape[1], gc["graph"].shape[1], cfg["s"], K)
+    bytes_launch = float(bq.sum())
+    achieved = bytes_launch / (launch_ms / 1e3) / 1e9
+    traffic = traffic_from_profile("c2_search_f32")
+    out = {
+        "metric": "queries/sec at recall@10>=0.95 (1Mx128, 1 GPU); achieved HBM GB/s vs peak",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": launch_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sift-shaped synthetic, base 1,000,000 x 128 integers 0..255 "
+                               "(fp32), NSSG R=50 alpha=60, 10,000 unindexed queries",
+                   "K": K, "L": L, "metric": "l2", "nq": int(len(q)), "n": int(base.shape[0]),
+                   "d": int(base.shape[1]), "R": int(gc["graph"].shape[1])},
+        "recall10": r10,
+        "oracle_recall10": next((r["recall10"] for r in sweep["rows"] if r["L"] == L), None),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_query": float(bq.mean()),
+                     "oracle_ndc_mean": float(np.mean(ondc)), "oracle_hops_mean": float(np.mean(ohops)),
+                     "gpu_ndc_mean": float(gndc.mean())},
+        "kernel_source": source_digest(),
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(base, gc, q, K, L, cfg, a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(base, gc, q, K, L, cfg, sample):
+    """The FP64 CPU oracle (Alg. 1, all host threads) on a bounded sample of
+    the same queries, scaled to queries/s."""
+    from oracle import core
+    m = sample or len(q)
+    qs = q[:m]
+    t = time.perf_counter()
+    core.search(base, gc["graph"], gc["entry_ids"], qs, K, L, cfg["metric"])
+    one = time.perf_counter() - t
+    reps = int(min(50, max(1, np.ceil(10.0 / max(one, 1e-3)))))  # about 10 s of CPU work
+    t = time.perf_counter()
+    for _ in range(reps):
+        core.search(base, gc["graph"], gc["entry_ids"], qs, K, L, cfg["metric"])
+    el = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"cpu oracle: {reps} x {m} queries in {el:.2f}s on {threads} threads")
+    return {"value": reps * m / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} passes over {m} of the {len(q)} queries, same graph, L={L}, "
+                      f"K={K}, FP64, {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()
