@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the CPU baseline")
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--hash-log2", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the index and every query "
@@ -116,7 +117,8 @@ def main():
     tq = torch.from_numpy(q).to(dev)
     ids = torch.empty((len(q), K), dtype=torch.int32, device=dev)
     dd = torch.empty((len(q), K), dtype=torch.float32, device=dev)
-    kw = dict(out=(ids, dd), waves_per_block=a.waves_per_block, hash_log2=a.hash_log2)
+    kw = dict(out=(ids, dd), waves_per_block=a.waves_per_block, hash_log2=a.hash_log2,
+              gather_variant=a.variant)
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(a.warmup):
@@ -125,7 +127,7 @@ def main():
     gids = ids.cpu().numpy()
     r10 = recall_at(gids, gt, 10)
     _, _, gndc, ghops = search(tb, tg, te, tq, K, L, stats=True, waves_per_block=a.waves_per_block,
-                               hash_log2=a.hash_log2)
+                               hash_log2=a.hash_log2, gather_variant=a.variant)
     gndc = gndc.cpu().numpy()
     log(f"warmup done; GPU recall@10 = {r10:.4f}; GPU NDC {gndc.mean():.1f} "
         f"(oracle {np.mean(ondc):.1f})")

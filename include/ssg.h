@@ -66,6 +66,7 @@ typedef struct {
     int32_t waves_per_block;  /* wavefronts (queries) per workgroup; 0 = default */
     int32_t* out_ndc;         /* DEVICE int32[nq] distance computations, or NULL */
     int32_t* out_hops;        /* DEVICE int32[nq] expansions, or NULL */
+    int32_t gather_variant;   /* alternative gather shape (tuning); 0 = default */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144

@@ -33,7 +33,7 @@ class SSGError(RuntimeError):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("exact_visited", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
-                ("out_hops", ctypes.c_void_p)]
+                ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32)]
 
 
 _lock = threading.Lock()

@@ -32,7 +32,8 @@ def _need_cuda(name, t, dtypes=None):
 
 def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
-           waves_per_block: int = 0, hash_log2: int = 0, out=None, stream=None):
+           waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0, out=None,
+           stream=None):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -69,7 +70,7 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
         hops = torch.empty(nq, dtype=torch.int32, device=dev)
     opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
                            None if ndc is None else ndc.data_ptr(),
-                           None if hops is None else hops.data_ptr())
+                           None if hops is None else hops.data_ptr(), gather_variant)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,

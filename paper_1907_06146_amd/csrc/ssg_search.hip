@@ -92,6 +92,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t id, uint32_t mask) {
 // A "chunk" is 16 bytes of a stored vector: 4 f32, 8 bf16 or 16 fp8 values.
 struct F32T {
   static constexpr int kEpc = 4;
+  static constexpr bool kScaled = false;
   __device__ static __forceinline__ void decode(uint4 c, float* x) {
     x[0] = __uint_as_float(c.x);
     x[1] = __uint_as_float(c.y);
@@ -101,6 +102,7 @@ struct F32T {
 };
 struct BF16T {
   static constexpr int kEpc = 8;
+  static constexpr bool kScaled = false;
   __device__ static __forceinline__ void decode(uint4 c, float* x) {
     const uint32_t w[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
@@ -114,6 +116,7 @@ struct BF16T {
 // bit placement for normal codes and by one multiply for subnormal codes.
 struct FP8T {
   static constexpr int kEpc = 16;
+  static constexpr bool kScaled = true;
   __device__ static __forceinline__ float one(uint32_t b) {
     uint32_t s = (b & 0x80u) << 24;
     uint32_t e = (b >> 3) & 0xFu;
@@ -156,8 +159,10 @@ struct Args {
 
 // ------------------------------------------------------------------ kernel
 // T: stored element type; DC: chunks per vector (0 = runtime, query in LDS);
-// G: lanes cooperating on one candidate; PREG: pool registers per lane.
-template <typename T, int DC, int G, int PREG>
+// G: lanes cooperating on one candidate; NP: gather passes whose loads are
+// all issued before the first is consumed (NP * 64 / G candidates in flight);
+// PREG: pool registers per lane (pool capacity 64 * PREG).
+template <typename T, int DC, int G, int NP, int PREG>
 __global__ __launch_bounds__(256) void search_kernel(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int EPC = T::kEpc;
@@ -165,6 +170,7 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   constexpr int NCH = DC > 0 ? (DC + G - 1) / G : 1;    // chunks per lane
   constexpr int LCAP = 64 * PREG;
   constexpr bool kQueryInRegs = DC > 0;
+  constexpr bool kScaled = T::kScaled;
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -175,40 +181,48 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   uint64_t* stage = reinterpret_cast<uint64_t*>(my);
   uint64_t* bkeys = stage + LCAP;
   uint32_t* bids = reinterpret_cast<uint32_t*>(bkeys + 64);
-  float* qlds = reinterpret_cast<float*>(bids + 64);  // runtime-DC query copy
-  uint32_t* table = reinterpret_cast<uint32_t*>(qlds + (kQueryInRegs ? 0 : a.dc * EPC));
+  float* qlds = reinterpret_cast<float*>(bids + 64);  // runtime-DC query (and scale) copy
+  const int qlds_floats = kQueryInRegs ? 0 : a.dc * EPC * (kScaled ? 2 : 1);
+  uint32_t* table = reinterpret_cast<uint32_t*>(qlds + qlds_floats);
 
   const int g = lane % G;
   const int grp = lane / G;
   const float* q = a.queries + (size_t)qid * a.d;
   const bool ip = a.metric == 1;
   const int L = a.L;
+  const int R = a.R;
 
-  // query fragment: lane g holds chunks g, g+G, ... (EPC floats each)
+  // query (and fp8 scale) fragment: lane g holds chunks g, g+G, ...
   float qf[kQueryInRegs ? NCH * EPC : 1];
+  float sf[kQueryInRegs && kScaled ? NCH * EPC : 1];
   if constexpr (kQueryInRegs) {
 #pragma unroll
     for (int t = 0; t < NCH; ++t) {
       const int ch = g + G * t;
-      if (DC % G == 0 || ch < DC) {
+      const bool ok = DC % G == 0 || ch < DC;
 #pragma unroll
-        for (int e = 0; e < EPC; e += 4) {
-          float4 v = *reinterpret_cast<const float4*>(q + ch * EPC + e);
-          qf[t * EPC + e] = v.x;
-          qf[t * EPC + e + 1] = v.y;
-          qf[t * EPC + e + 2] = v.z;
-          qf[t * EPC + e + 3] = v.w;
+      for (int e = 0; e < EPC; e += 4) {
+        float4 v = ok ? *reinterpret_cast<const float4*>(q + ch * EPC + e) : make_float4(0, 0, 0, 0);
+        qf[t * EPC + e] = v.x;
+        qf[t * EPC + e + 1] = v.y;
+        qf[t * EPC + e + 2] = v.z;
+        qf[t * EPC + e + 3] = v.w;
+        if constexpr (kScaled) {
+          float4 w = ok ? *reinterpret_cast<const float4*>(a.dim_scale + ch * EPC + e)
+                        : make_float4(0, 0, 0, 0);
+          sf[t * EPC + e] = w.x;
+          sf[t * EPC + e + 1] = w.y;
+          sf[t * EPC + e + 2] = w.z;
+          sf[t * EPC + e + 3] = w.w;
         }
-      } else {
-#pragma unroll
-        for (int e = 0; e < EPC; ++e) qf[t * EPC + e] = 0.f;
       }
     }
   } else {
-    for (int j = lane; j < a.d; j += 64) qlds[j] = q[j];
+    for (int j = lane; j < a.d; j += 64) {
+      qlds[j] = q[j];
+      if constexpr (kScaled) qlds[a.d + j] = a.dim_scale[j];
+    }
   }
-  // fp8: fold the per-dimension scale into the chunk decode below
-  const float* scale = a.dim_scale;
 
   // visited structure
   const uint32_t hmask = (1u << a.hash_log2) - 1u;
@@ -219,68 +233,79 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   int hcount = 0;                         // ids inserted since the last clear
   const int hlimit = (int)((hmask + 1u) >> 1);
 
-  // distance of the candidates in bids[0..m) -> bkeys[0..m)
+  // one distance term; the fp8 value is code * scale rounded to fp32 first
+  auto term = [&](float acc, float qv, float xv) -> float {
+    if (ip) return fmaf(qv, xv, acc);
+    const float df = qv - xv;
+    return fmaf(df, df, acc);
+  };
+
+  // distances of the candidates in bids[0..m) -> bkeys[0..m)
   auto batch_keys = [&](int m) {
-    for (int c0 = 0; c0 < m; c0 += CPP) {
-      const int c = c0 + grp;
-      const bool valid = c < m;
-      const uint32_t id = valid ? bids[c] : 0u;
-      const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)id * a.dc * 16);
-      float acc = 0.f;
-      if constexpr (kQueryInRegs) {
-        uint4 buf[NCH];
+    for (int c0 = 0; c0 < m; c0 += CPP * NP) {
+      uint32_t idp[NP];
+      bool vp[NP];
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const int ch = g + G * t;
-          if (valid && (DC % G == 0 || ch < DC)) buf[t] = vec[ch];
-          else buf[t] = make_uint4(0, 0, 0, 0);
+      for (int p = 0; p < NP; ++p) {
+        const int c = c0 + p * CPP + grp;
+        vp[p] = c < m;
+        idp[p] = vp[p] ? bids[c] : 0u;
+      }
+      float acc[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+      if constexpr (kQueryInRegs) {
+        uint4 buf[NP][NCH];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)idp[p] * a.dc * 16);
+#pragma unroll
+          for (int t = 0; t < NCH; ++t) {
+            const int ch = g + G * t;
+            if (vp[p] && (DC % G == 0 || ch < DC)) buf[p][t] = vec[ch];
+            else buf[p][t] = make_uint4(0, 0, 0, 0);
+          }
         }
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const int ch = g + G * t;
-          if (DC % G == 0 || ch < DC) {
-            float x[EPC];
-            T::decode(buf[t], x);
-            if (scale) {
+        for (int p = 0; p < NP; ++p) {
 #pragma unroll
-              for (int e = 0; e < EPC; ++e) x[e] *= scale[ch * EPC + e];
-            }
+          for (int t = 0; t < NCH; ++t) {
+            const int ch = g + G * t;
+            if (DC % G == 0 || ch < DC) {
+              float x[EPC];
+              T::decode(buf[p][t], x);
 #pragma unroll
-            for (int e = 0; e < EPC; ++e) {
-              if (ip) {
-                acc = fmaf(qf[t * EPC + e], x[e], acc);
-              } else {
-                const float df = qf[t * EPC + e] - x[e];
-                acc = fmaf(df, df, acc);
+              for (int e = 0; e < EPC; ++e) {
+                const float xv = kScaled ? __fmul_rn(x[e], sf[t * EPC + e]) : x[e];
+                acc[p] = term(acc[p], qf[t * EPC + e], xv);
               }
             }
           }
         }
       } else {
-        if (valid) {
-          for (int ch = g; ch < a.dc; ch += G) {
-            float x[EPC];
-            T::decode(vec[ch], x);
-            if (scale) {
 #pragma unroll
-              for (int e = 0; e < EPC; ++e) x[e] *= scale[ch * EPC + e];
-            }
+        for (int p = 0; p < NP; ++p) {
+          if (vp[p]) {
+            const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)idp[p] * a.dc * 16);
+#pragma unroll 4
+            for (int ch = g; ch < a.dc; ch += G) {
+              float x[EPC];
+              T::decode(vec[ch], x);
 #pragma unroll
-            for (int e = 0; e < EPC; ++e) {
-              const float qv = qlds[ch * EPC + e];
-              if (ip) {
-                acc = fmaf(qv, x[e], acc);
-              } else {
-                const float df = qv - x[e];
-                acc = fmaf(df, df, acc);
+              for (int e = 0; e < EPC; ++e) {
+                const float xv = kScaled ? __fmul_rn(x[e], qlds[a.d + ch * EPC + e]) : x[e];
+                acc[p] = term(acc[p], qlds[ch * EPC + e], xv);
               }
             }
           }
         }
       }
 #pragma unroll
-      for (int off = G / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      if (valid && g == 0) bkeys[c] = make_key(ip ? -acc : acc, id);
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, 64);
+        if (vp[p] && g == 0) bkeys[c0 + p * CPP + grp] = make_key(ip ? -acc[p] : acc[p], idp[p]);
+      }
     }
     wave_sync();
   };
@@ -311,7 +336,8 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   int size = 0;
   int ndc = 0, hops = 0;
 
-  // ---- entry: the nearest navigating node seeds the pool
+  // ---- entry: the nearest navigating node seeds the pool and is expanded first
+  uint32_t p;
   {
     uint64_t best = kNoKey;
     for (int e0 = 0; e0 < a.s; e0 += 64) {
@@ -325,35 +351,21 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) best = min(best, shfl_xor64(best, off));
     ndc = a.s;
-    if (lane == 0) pool[0] = best;
+    if (lane == 0) pool[0] = best | 1ull;
     size = 1;
-    if (lane == 0) visit(key_id(best));
+    p = key_id(best);
+    if (lane == 0) visit(p);
     hcount = 1;
     wave_sync();
   }
+  uint32_t nb = lane < R ? a.graph[(size_t)p * R + lane] : kSent;  // row being expanded
 
   for (;;) {
-    // 1. first unchecked entry
-    int pos = -1;
-    uint32_t p = 0;
-#pragma unroll
-    for (int k = 0; k < PREG; ++k) {
-      if (pos < 0) {
-        const uint64_t um = __ballot((pool[k] & 1ull) == 0ull);
-        if (um) {
-          const int l = __builtin_ctzll(um);
-          pos = k * 64 + l;
-          p = key_id(readlane64(pool[k], l));
-          if (lane == l) pool[k] |= 1ull;
-        }
-      }
-    }
-    if (pos < 0) break;
     ++hops;
     if (hops > a.n + 1) break;  // cannot happen (each node is expanded at most once); bounds the loop
 
     // visited table maintenance: rebuild from the pool when half full
-    if (!a.exact && hcount + a.R > hlimit) {
+    if (!a.exact && hcount + R > hlimit) {
       for (int i = lane; i <= (int)hmask; i += 64) table[i] = kSent;
       wave_sync();
 #pragma unroll
@@ -363,51 +375,81 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
       hcount = size;
     }
 
-    // 2-4. neighbour row, visited filter, compaction
-    const uint32_t nb = lane < a.R ? a.graph[(size_t)p * a.R + lane] : kSent;
+    // visited filter and compaction of the row's new ids
     const bool fresh = nb != kSent && visit(nb);
     const uint64_t fm = __ballot(fresh);
     const int m = __popcll(fm);
     if (fresh) bids[lane_prefix(fm)] = nb;
     wave_sync();
-    if (m == 0) continue;
     hcount += m;
     ndc += m;
 
-    // 5. distances
-    batch_keys(m);
+    uint64_t b = kNoKey;
+    if (m > 0) {
+      batch_keys(m);
+      b = lane < m ? bkeys[lane] : kNoKey;
+    }
 
-    // 6. rank-based merge of the m new keys into the pool, truncated to L
-    const uint64_t b = lane < m ? bkeys[lane] : kNoKey;
-    int rank = 0, qcnt = 0;
-    int shift[PREG];
+    // next expansion, decided before the merge so its row read overlaps it:
+    // the smallest unchecked key u of (pool + new keys) is kept iff fewer
+    // than L keys precede it; otherwise every kept entry is checked.
+    uint64_t u = kNoKey;
 #pragma unroll
-    for (int k = 0; k < PREG; ++k) shift[k] = 0;
-    for (int j = 0; j < m; ++j) {
-      const uint64_t bj = readlane64(b, j);
-      int r = 0;
+    for (int k = 0; k < PREG; ++k) {
+      const uint64_t um = __ballot((pool[k] & 1ull) == 0ull);
+      if (u == kNoKey && um) u = readlane64(pool[k], __builtin_ctzll(um));
+    }
+    uint64_t bmin = b;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) bmin = min(bmin, shfl_xor64(bmin, off));
+    u = min(u, bmin);
+    int rank_u = __popcll(__ballot(b < u));
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
+    const bool more = u != kNoKey && rank_u < L;
+    uint32_t nb_next = kSent;
+    if (more) {
+      p = key_id(u);
+      nb_next = lane < R ? a.graph[(size_t)p * R + lane] : kSent;
+    }
+
+    // rank-based merge of the m new keys into the pool, truncated to L
+    if (m > 0) {
+      int rank = 0, qcnt = 0;
+      int shift[PREG];
+#pragma unroll
+      for (int k = 0; k < PREG; ++k) shift[k] = 0;
+      for (int j = 0; j < m; ++j) {
+        const uint64_t bj = readlane64(b, j);
+        int r = 0;
+#pragma unroll
+        for (int k = 0; k < PREG; ++k) {
+          r += __popcll(__ballot(pool[k] < bj));
+          shift[k] += bj < pool[k] ? 1 : 0;
+        }
+        if (lane == j) rank = r;
+        qcnt += bj < b ? 1 : 0;
+      }
 #pragma unroll
       for (int k = 0; k < PREG; ++k) {
-        r += __popcll(__ballot(pool[k] < bj));
-        shift[k] += bj < pool[k] ? 1 : 0;
+        const int np = k * 64 + lane + shift[k];
+        if (pool[k] != kNoKey && np < L) stage[np] = pool[k];
       }
-      if (lane == j) rank = r;
-      qcnt += bj < b ? 1 : 0;
-    }
+      if (lane < m && rank + qcnt < L) stage[rank + qcnt] = b;
+      wave_sync();
+      size = min(L, size + m);
 #pragma unroll
-    for (int k = 0; k < PREG; ++k) {
-      const int np = k * 64 + lane + shift[k];
-      if (pool[k] != kNoKey && np < L) stage[np] = pool[k];
+      for (int k = 0; k < PREG; ++k) {
+        const int i = k * 64 + lane;
+        pool[k] = i < size ? stage[i] : kNoKey;
+      }
+      wave_sync();
     }
-    if (lane < m && rank + qcnt < L) stage[rank + qcnt] = b;
-    wave_sync();
-    size = min(L, size + m);
+    if (!more) break;
 #pragma unroll
-    for (int k = 0; k < PREG; ++k) {
-      const int i = k * 64 + lane;
-      pool[k] = i < size ? stage[i] : kNoKey;
-    }
-    wave_sync();
+    for (int k = 0; k < PREG; ++k)
+      if (pool[k] == u) pool[k] |= 1ull;  // mark the next expansion checked
+    nb = nb_next;
   }
 
   // ---- output: first K pool entries, padded
@@ -454,64 +496,76 @@ struct Launch {
   bool query_in_regs = false;
 };
 
-template <typename T, int DC, int G>
+template <typename T, int DC, int G, int NP>
 KernelFn pick_preg(int preg) {
   switch (preg) {
-    case 1: return search_kernel<T, DC, G, 1>;
-    case 2: return search_kernel<T, DC, G, 2>;
-    case 4: return search_kernel<T, DC, G, 4>;
-    default: return search_kernel<T, DC, G, 8>;
+    case 1: return search_kernel<T, DC, G, NP, 1>;
+    case 2: return search_kernel<T, DC, G, NP, 2>;
+    case 4: return search_kernel<T, DC, G, NP, 4>;
+    default: return search_kernel<T, DC, G, NP, 8>;
   }
 }
 
 // Launch tables: compile-time chunk counts for the dimensions of the paper's
 // datasets (Table 2: 96, 100, 128, 300, 960) and of the tiny workload (32).
-// G is chosen so each lane keeps at most 32 query floats in registers; other
-// shapes use the runtime-chunk kernel (DC = 0) with the query in LDS.
+// G and NP set how many candidates' loads are in flight per wavefront
+// (NP * 64 / G) and how many query floats a lane keeps in registers
+// (EPC * DC / G). `variant` selects alternative gather shapes for tuning;
+// shapes not listed use the runtime-chunk kernel (query in LDS).
 template <typename T>
 struct Table;
 template <>
 struct Table<F32T> {
-  static Launch pick(int dc, int preg) {
+  static Launch pick(int dc, int preg, int variant) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 8: l.fn = pick_preg<F32T, 8, 2>(preg); return l;     // d = 32
-      case 24: l.fn = pick_preg<F32T, 24, 8>(preg); return l;   // d = 96
-      case 25: l.fn = pick_preg<F32T, 25, 8>(preg); return l;   // d = 100
-      case 32: l.fn = pick_preg<F32T, 32, 8>(preg); return l;   // d = 128
-      case 75: l.fn = pick_preg<F32T, 75, 16>(preg); return l;  // d = 300
+      case 8: l.fn = pick_preg<F32T, 8, 2, 1>(preg); return l;    // d = 32: 32 in flight
+      case 24: l.fn = pick_preg<F32T, 24, 4, 1>(preg); return l;  // d = 96: 16
+      case 25: l.fn = pick_preg<F32T, 25, 4, 1>(preg); return l;  // d = 100: 16
+      case 32:                                                     // d = 128
+        switch (variant) {
+          case 1: l.fn = pick_preg<F32T, 32, 8, 1>(preg); return l;  // 8 in flight
+          case 2: l.fn = pick_preg<F32T, 32, 8, 2>(preg); return l;  // 16
+          case 3: l.fn = pick_preg<F32T, 32, 4, 2>(preg); return l;  // 32
+          default: l.fn = pick_preg<F32T, 32, 4, 1>(preg); return l; // 16
+        }
+      case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg); return l;  // d = 300: 8
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<F32T, 0, 16>(preg);
+    l.fn = pick_preg<F32T, 0, 16, 2>(preg);
     return l;
   }
 };
 template <>
 struct Table<BF16T> {
-  static Launch pick(int dc, int preg) {
+  static Launch pick(int dc, int preg, int variant) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 12: l.fn = pick_preg<BF16T, 12, 4>(preg); return l;  // d = 96
-      case 16: l.fn = pick_preg<BF16T, 16, 4>(preg); return l;  // d = 128
+      case 12: l.fn = pick_preg<BF16T, 12, 4, 1>(preg); return l;  // d = 96
+      case 16:                                                      // d = 128
+        switch (variant) {
+          case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg); return l;
+          default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg); return l;
+        }
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<BF16T, 0, 16>(preg);
+    l.fn = pick_preg<BF16T, 0, 16, 2>(preg);
     return l;
   }
 };
 template <>
 struct Table<FP8T> {
-  static Launch pick(int dc, int preg) {
+  static Launch pick(int dc, int preg, int) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 6: l.fn = pick_preg<FP8T, 6, 4>(preg); return l;  // d = 96
-      case 8: l.fn = pick_preg<FP8T, 8, 4>(preg); return l;  // d = 128
+      case 6: l.fn = pick_preg<FP8T, 6, 4, 1>(preg); return l;  // d = 96
+      case 8: l.fn = pick_preg<FP8T, 8, 4, 1>(preg); return l;  // d = 128
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<FP8T, 0, 16>(preg);
+    l.fn = pick_preg<FP8T, 0, 16, 2>(preg);
     return l;
   }
 };
@@ -592,10 +646,12 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   const int preg = preg_for(L);
   const int epc = dtype == SSG_F32 ? 4 : dtype == SSG_BF16 ? 8 : 16;
   const int dc = d / epc;
-  Launch lc = dtype == SSG_F32    ? Table<F32T>::pick(dc, preg)
-              : dtype == SSG_BF16 ? Table<BF16T>::pick(dc, preg)
-                                  : Table<FP8T>::pick(dc, preg);
-  int wpb = o.waves_per_block > 0 ? o.waves_per_block : 4;
+  Launch lc = dtype == SSG_F32    ? Table<F32T>::pick(dc, preg, o.gather_variant)
+              : dtype == SSG_BF16 ? Table<BF16T>::pick(dc, preg, o.gather_variant)
+                                  : Table<FP8T>::pick(dc, preg, o.gather_variant);
+  // one wavefront per workgroup measured fastest on the 1M x 128 workload
+  // (finer-grained dispatch, no LDS fragmentation across waves)
+  int wpb = o.waves_per_block > 0 ? o.waves_per_block : 1;
   if (wpb > 4) return fail(SSG_EINVAL, "waves_per_block must be in [1, 4]");
   Args a{};
   a.base = static_cast<const unsigned char*>(base);
@@ -618,7 +674,8 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.out_hops = o.out_hops;
   a.exact = o.exact_visited ? 1 : 0;
   const int lcap = 64 * preg;
-  size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 + (lc.query_in_regs ? 0 : (size_t)d * 4);
+  size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 +
+                 (lc.query_in_regs ? 0 : (size_t)d * 4 * (dtype == SSG_FP8E4M3 ? 2 : 1));
   size_t table;
   if (a.exact) {
     if (n > SSG_EXACT_VISITED_MAX_N)
