@@ -67,6 +67,12 @@ typedef struct {
     int32_t* out_ndc;         /* DEVICE int32[nq] distance computations, or NULL */
     int32_t* out_hops;        /* DEVICE int32[nq] expansions, or NULL */
     int32_t gather_variant;   /* alternative gather shape (tuning); 0 = default */
+    const float* base_f32;    /* DEVICE n x d FP32 vectors: when set, the first
+                                 rerank_k pool entries are re-scored exactly in
+                                 FP32 against them and re-sorted before the K
+                                 results are written (precision form: search on
+                                 BF16/FP8, rerank in FP32); NULL = no rerank */
+    int32_t rerank_k;         /* entries to rerank, 0 = K; capped at L */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144
@@ -107,6 +113,21 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
                   const float* queries, int64_t nq, int32_t K, int32_t L, int32_t metric,
                   uint32_t* out_ids, float* out_dists, const ssg_search_opts* opts,
                   void* stream);
+
+/*
+ * ssg_quantize -- build a reduced-precision copy of the base vectors for the
+ * precision form of the search (storage format only; not from the paper,
+ * which computes exact distances on full-precision vectors, Sec. 6.1).
+ *   base_f32   DEVICE float n x d.
+ *   dtype      SSG_BF16: out is uint16 n x d, round-to-nearest-even bfloat16.
+ *              SSG_FP8E4M3: dim_scale (DEVICE float[d], written) receives
+ *              s_j = max_i |x_ij| / 448 (1 for an all-zero column) and out is
+ *              uint8 n x d holding OCP E4M3 codes of x_ij / s_j, rounded to
+ *              nearest even and saturated at +-448.
+ * Asynchronous on `stream`; returns SSG_OK or SSG_EINVAL / SSG_EDEVICE.
+ */
+int ssg_quantize(const float* base_f32, int64_t n, int32_t d, int32_t dtype, float* dim_scale,
+                 void* out, void* stream);
 
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);

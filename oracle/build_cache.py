@@ -54,10 +54,19 @@ def build(name: str, sweep: bool, expand: str, sweep_only: bool = False):
             log("knn loaded", knn.shape)
         else:
             t = time.time()
-            knn, _ = core.knn_graph(base, cfg["knn_k"], verbose=cfg["n"] > 100_000)
+            if cfg.get("knn", "exact") == "ivf":
+                knn, _ = core.knn_graph_ivf(base, cfg["knn_k"], cfg["nlist"], cfg["nprobe"],
+                                            cfg["seed"] + 7, verbose=True)
+                log("ivf knn", f"{time.time() - t:.1f}s", "accuracy", core.knn_accuracy(base, knn))
+                knn = core.knn_refine(base, knn, cfg["refine_J"], cfg["refine_rounds"])
+            else:
+                knn, _ = core.knn_graph(base, cfg["knn_k"], verbose=cfg["n"] > 100_000)
             os.makedirs(os.path.dirname(kpath), exist_ok=True)
             np.save(kpath, knn)
             log("knn built", f"{time.time() - t:.1f}s")
+        acc = core.knn_accuracy(base, knn, sample=300)
+        meta.update(knn_method=cfg.get("knn", "exact"), knn_acc_1nn=acc[0], knn_acc_k=acc[1])
+        log("knn accuracy (1-NN, K-NN)", acc)
         t = time.time()
         res = core.nssg_build(base, knn, cfg["l"], cfg["R"], cfg["alpha"], entry, expand)
         g = res["graph"]

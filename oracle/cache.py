@@ -3,7 +3,10 @@
 A cache directory ``data/<workload>/`` holds plain ``.npy`` arrays and a
 ``meta.json`` with the build parameters, the readings used and checksums:
 
-  graph.npy      uint32 [n, R]  NSSG rows: neighbour ids, then 0xFFFFFFFF
+  graph_off.npy  int64 [n+1]   NSSG rows in compressed form: row i is
+  graph_ids.npy  uint32 [nnz]   graph_ids[graph_off[i]:graph_off[i+1]]; the
+                                fixed-width [n, R] matrix (ids, then
+                                0xFFFFFFFF) is rebuilt on load, R = meta["R"]
   entry_ids.npy  uint32 [s]     navigating nodes
   dfs_edges.npy  uint32 [k, 2]  edges added by DFS spanning (w, u)
   gt_ids.npy     uint32 [nq, Kg] exact ground truth, (dist, id) order
@@ -34,10 +37,34 @@ def path(name: str) -> str:
     return os.path.join(data_root(), name)
 
 
+SENT = 0xFFFFFFFF
+
+
+def _to_csr(g: np.ndarray):
+    valid = g != SENT
+    off = np.zeros(g.shape[0] + 1, np.int64)
+    np.cumsum(valid.sum(1), out=off[1:])
+    return off, g[valid].astype(np.uint32)
+
+
+def _from_csr(off: np.ndarray, ids: np.ndarray, R: int) -> np.ndarray:
+    n = len(off) - 1
+    deg = np.diff(off)
+    g = np.full((n, R), SENT, np.uint32)
+    col = np.arange(len(ids)) - np.repeat(off[:-1], deg)
+    g[np.repeat(np.arange(n), deg), col] = ids
+    return g
+
+
 def save(name: str, arrays: dict, meta: dict) -> str:
     d = path(name)
     os.makedirs(d, exist_ok=True)
     for k, v in arrays.items():
+        if k == "graph":
+            off, ids = _to_csr(v)
+            np.save(os.path.join(d, "graph_off.npy"), off)
+            np.save(os.path.join(d, "graph_ids.npy"), ids)
+            continue
         np.save(os.path.join(d, k + ".npy"), v)
     m = dict(meta)
     m["format_version"] = FORMAT_VERSION
@@ -57,9 +84,15 @@ def load_meta(name: str):
 
 
 def load(name: str, key: str, mmap: bool = False):
+    if key == "graph":
+        off = np.load(os.path.join(path(name), "graph_off.npy"), allow_pickle=False)
+        ids = np.load(os.path.join(path(name), "graph_ids.npy"), allow_pickle=False)
+        return _from_csr(off, ids, load_meta(name)["R"])
     p = os.path.join(path(name), key + ".npy")
     return np.load(p, mmap_mode="r" if mmap else None, allow_pickle=False)
 
 
 def exists(name: str, key: str) -> bool:
+    if key == "graph":
+        key = "graph_off"
     return os.path.exists(os.path.join(path(name), key + ".npy"))

@@ -150,6 +150,42 @@ int orc_rerank(const float *base, int64_t n, int d, const float *Q, int64_t nq,
     return bad ? -2 : 0;
 }
 
+/* One refinement pass of an approximate kNN graph: the candidates of node i
+ * are its current list plus the lists of its first J neighbours; the K
+ * nearest by exact FP64 key (ties by id, i itself excluded) form the new row.
+ * knn and out are n x K (may not alias). */
+int orc_knn_refine(const float *base, int64_t n, int d, const uint32_t *knn, int K, int J,
+                   uint32_t *out) {
+    if (!base || !knn || !out || n < 2 || d < 1 || K < 1 || J < 0 || J > K) return -1;
+#pragma omp parallel
+    {
+        uint32_t *stamp = (uint32_t *)calloc((size_t)n, sizeof(uint32_t));
+        cand_t *top = (cand_t *)malloc(sizeof(cand_t) * (size_t)K);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            uint32_t tag = (uint32_t)i + 1u;
+            int cnt = 0;
+            const float *xi = base + (size_t)i * d;
+            stamp[i] = tag;
+            const uint32_t *row = knn + (size_t)i * K;
+            for (int a = -1; a < J; ++a) {
+                const uint32_t *src = a < 0 ? row : (row[a] == SENT ? NULL : knn + (size_t)row[a] * K);
+                if (!src) continue;
+                for (int t = 0; t < K; ++t) {
+                    uint32_t v = src[t];
+                    if (v == SENT || v >= (uint64_t)n || stamp[v] == tag) continue;
+                    stamp[v] = tag;
+                    topk_push(top, &cnt, K, key_dist(xi, base + (size_t)v * d, d, 0), v);
+                }
+            }
+            for (int t = 0; t < K; ++t) out[(size_t)i * K + t] = t < cnt ? top[t].id : SENT;
+        }
+        free(stamp);
+        free(top);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------ SSG pruning */
 
 /* Greedy SSG edge selection around node i (the pruning rule of Alg. 2, as

@@ -11,3 +11,9 @@ def search(*args, **kwargs):
     """See ``binding.search``."""
     from .binding import search as _search
     return _search(*args, **kwargs)
+
+
+def quantize(*args, **kwargs):
+    """See ``binding.quantize``."""
+    from .binding import quantize as _quantize
+    return _quantize(*args, **kwargs)

@@ -20,8 +20,8 @@ SSG_F32, SSG_BF16, SSG_FP8E4M3 = 0, 1, 2
 SENTINEL = 0xFFFFFFFF
 L_MAX, R_MAX, K_MAX = 512, 64, 4096
 
-EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_search_workspace_bytes", "ssg_validate_graph",
-           "ssg_last_error", "ssg_version")
+EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_bytes",
+           "ssg_validate_graph", "ssg_last_error", "ssg_version")
 
 
 class SSGError(RuntimeError):
@@ -33,7 +33,8 @@ class SSGError(RuntimeError):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("exact_visited", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
-                ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32)]
+                ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
+                ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -55,6 +56,8 @@ def lib() -> ctypes.CDLL:
             L.ssg_search_ex.argtypes = [P, i64, i32, i32, P, P, i32, P, i32, P, i64, i32, i32,
                                         i32, P, P, ctypes.POINTER(SearchOpts), P]
             L.ssg_search_ex.restype = ctypes.c_int
+            L.ssg_quantize.argtypes = [P, i64, i32, i32, P, P, P]
+            L.ssg_quantize.restype = ctypes.c_int
             L.ssg_search_workspace_bytes.argtypes = [i64, i64, i32, i32, i32]
             L.ssg_search_workspace_bytes.restype = sz
             L.ssg_validate_graph.argtypes = [P, i64, i32]

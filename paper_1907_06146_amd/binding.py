@@ -32,8 +32,8 @@ def _need_cuda(name, t, dtypes=None):
 
 def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
-           waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0, out=None,
-           stream=None):
+           waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0,
+           base_f32=None, rerank_k: int = 0, out=None, stream=None):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -42,6 +42,8 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     queries    [nq, d] float32
     Returns (ids [nq, K] int32 with -1 padding, dists [nq, K] float32) and,
     with stats=True, also (ndc [nq] int32, hops [nq] int32).
+    base_f32   optional [n, d] float32: rerank the first rerank_k (0 = K) pool
+               entries exactly in FP32 before writing the K results.
     """
     _need_cuda("base", base, tuple(_DTYPES))
     _need_cuda("graph", graph, (torch.int32, torch.uint32))
@@ -57,6 +59,10 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     dtype = _DTYPES[base.dtype]
     if dtype == _lib.SSG_FP8E4M3:
         _need_cuda("dim_scale", dim_scale, (torch.float32,))
+    if base_f32 is not None:
+        _need_cuda("base_f32", base_f32, (torch.float32,))
+        if tuple(base_f32.shape) != (n, d):
+            raise ValueError("base_f32 must have the shape of base")
     nq = queries.shape[0]
     dev = base.device
     if out is None:
@@ -70,7 +76,8 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
         hops = torch.empty(nq, dtype=torch.int32, device=dev)
     opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
                            None if ndc is None else ndc.data_ptr(),
-                           None if hops is None else hops.data_ptr(), gather_variant)
+                           None if hops is None else hops.data_ptr(), gather_variant,
+                           None if base_f32 is None else base_f32.data_ptr(), rerank_k)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,
@@ -80,3 +87,27 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     if stats:
         return ids, dd, ndc, hops
     return ids, dd
+
+
+def quantize(base_f32, dtype: str, stream=None):
+    """Reduced-precision copy of FP32 base vectors, built by the library's
+    kernels. dtype "bf16" -> (bfloat16 [n, d], None); "fp8" -> (uint8 E4M3
+    codes [n, d], per-dimension scale float32 [d])."""
+    _need_cuda("base_f32", base_f32, (torch.float32,))
+    n, d = base_f32.shape
+    dev = base_f32.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    if dtype == "bf16":
+        out = torch.empty((n, d), dtype=torch.bfloat16, device=dev)
+        rc = _lib.lib().ssg_quantize(_ptr(base_f32), n, d, _lib.SSG_BF16, None, _ptr(out),
+                                     ctypes.c_void_p(st.cuda_stream))
+        _lib.check(rc)
+        return out, None
+    if dtype == "fp8":
+        out = torch.empty((n, d), dtype=torch.uint8, device=dev)
+        scale = torch.empty(d, dtype=torch.float32, device=dev)
+        rc = _lib.lib().ssg_quantize(_ptr(base_f32), n, d, _lib.SSG_FP8E4M3, _ptr(scale), _ptr(out),
+                                     ctypes.c_void_p(st.cuda_stream))
+        _lib.check(rc)
+        return out, scale
+    raise ValueError(f"unknown storage dtype {dtype}")

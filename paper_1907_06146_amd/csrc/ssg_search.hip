@@ -38,6 +38,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -155,6 +156,8 @@ struct Args {
   int32_t exact;       // 1: bitset visited
   int32_t hash_log2;   // hash mode: log2 table size
   int32_t lds_per_wave;
+  const float* base_f32;  // FP32 vectors for the final rerank, or null
+  int32_t rerank;         // pool entries to rerank (<= 64 * PREG)
 };
 
 // ------------------------------------------------------------------ kernel
@@ -452,6 +455,60 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
     nb = nb_next;
   }
 
+  // ---- optional rerank: exact FP32 keys of the first `rerank` pool entries
+  // against the FP32 vectors, re-sorted by (dist, id). The visited table is
+  // dead here, so its LDS holds the new keys; `stage` holds the sorted order.
+  if (a.base_f32 != nullptr) {
+    const int rr = min(a.rerank, size);
+    uint32_t* rids = bids;  // reused 64 at a time
+    uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
+    const int d4 = a.d >> 2;
+    const float4* q4 = reinterpret_cast<const float4*>(q);
+    for (int c0 = 0; c0 < rr; c0 += 64) {
+      const int cm = min(64, rr - c0);
+      // ids of pool entries c0 .. c0+cm-1 (entry i sits in lane i % 64, slot i / 64)
+#pragma unroll
+      for (int k = 0; k < PREG; ++k)
+        if (k == (c0 >> 6) && lane < cm) rids[lane] = key_id(pool[k]);
+      wave_sync();
+      for (int j0 = 0; j0 < cm; j0 += 4) {  // 16 lanes per candidate
+        const int c = j0 + (lane >> 4);
+        const int l16 = lane & 15;
+        float acc = 0.f;
+        uint32_t id = 0;
+        if (c < cm) {
+          id = rids[c];
+          const float4* x4 = reinterpret_cast<const float4*>(a.base_f32 + (size_t)id * a.d);
+          for (int ch = l16; ch < d4; ch += 16) {
+            const float4 x = x4[ch], qq = q4[ch];
+            acc = term(acc, qq.x, x.x);
+            acc = term(acc, qq.y, x.y);
+            acc = term(acc, qq.z, x.z);
+            acc = term(acc, qq.w, x.w);
+          }
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (c < cm && l16 == 0) rkeys[c0 + c] = make_key(ip ? -acc : acc, id);
+      }
+      wave_sync();
+    }
+    // rank sort: each key's slot is the number of smaller keys
+    for (int i = lane; i < rr; i += 64) {
+      const uint64_t ki = rkeys[i];
+      int r = 0;
+      for (int j = 0; j < rr; ++j) r += rkeys[j] < ki ? 1 : 0;
+      stage[r] = ki;
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) {
+      const int i = k * 64 + lane;
+      pool[k] = i < rr ? stage[i] : kNoKey;
+    }
+    wave_sync();
+  }
+
   // ---- output: first K pool entries, padded
   uint32_t* oid = a.out_ids + (size_t)qid * a.K;
   float* od = a.out_d + (size_t)qid * a.K;
@@ -471,6 +528,71 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   if (lane == 0) {
     if (a.out_ndc) a.out_ndc[qid] = ndc;
     if (a.out_hops) a.out_hops[qid] = hops;
+  }
+}
+
+// ------------------------------------------------------------------ quantizer
+// Storage forms for the precision variant of the search. Index preparation,
+// run once per base set, not part of a query.
+//   BF16: round-to-nearest-even of the upper 16 bits of each fp32 value.
+//   FP8 : OCP E4M3 (bias 7, max 448, no infinities) codes of x / s_j with the
+//         per-dimension scale s_j = max_i |x_ij| / 448 (1 if the column is 0),
+//         round-to-nearest-even, saturating at +-448.
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void absmax_cols_kernel(const float* x, int64_t n, int d, uint32_t* colmax) {
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  float m = 0.f;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) m = fmaxf(m, fabsf(x[(size_t)i * d + j]));
+  atomicMax(&colmax[j], __float_as_uint(m));  // non-negative floats order like their bits
+}
+
+__global__ void scale_cols_kernel(float* s, int d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  const float m = __uint_as_float(__float_as_uint(s[j]));
+  s[j] = m > 0.f ? __fdiv_rn(m, 448.f) : 1.f;
+}
+
+__device__ __forceinline__ uint32_t fp8_e4m3_rne(float v) {
+  const uint32_t sgn = (__float_as_uint(v) >> 24) & 0x80u;
+  const float a = fabsf(v);
+  if (!(a < 448.f)) return sgn | 0x7Eu;
+  if (a < 0.015625f) {  // below the smallest normal 2^-6: multiples of 2^-9
+    const uint32_t m = (uint32_t)__builtin_rintf(a * 512.f);  // 8 rounds up to 2^-6 = code 0x08
+    return sgn | m;
+  }
+  const uint32_t ua = __float_as_uint(a);
+  int e = (int)(ua >> 23) - 127;
+  uint32_t keep = (ua >> 20) & 7u;
+  const uint32_t rest = ua & 0xFFFFFu;
+  if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) ++keep;
+  if (keep == 8u) {
+    keep = 0u;
+    ++e;
+  }
+  const uint32_t mag = ((uint32_t)(e + 7) << 3) | keep;
+  return sgn | (mag > 0x7Eu ? 0x7Eu : mag);
+}
+
+__global__ void encode_kernel(const float* x, int64_t n, int d, int dtype, const float* scale,
+                              void* out) {
+  const int64_t total = n * (int64_t)d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x[i];
+    if (dtype == SSG_BF16) {
+      const uint32_t u = __float_as_uint(v);
+      static_cast<uint16_t*>(out)[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    } else {
+      const int j = (int)(i % d);
+      static_cast<uint8_t*>(out)[i] = (uint8_t)fp8_e4m3_rne(__fdiv_rn(v, scale[j]));
+    }
   }
 }
 
@@ -673,6 +795,14 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.out_ndc = o.out_ndc;
   a.out_hops = o.out_hops;
   a.exact = o.exact_visited ? 1 : 0;
+  a.base_f32 = o.base_f32;
+  a.rerank = 0;
+  if (o.base_f32) {
+    if (reinterpret_cast<uintptr_t>(o.base_f32) % 16)
+      return fail(SSG_EINVAL, "base_f32 must be 16-byte aligned");
+    if (o.rerank_k < 0) return fail(SSG_EINVAL, "rerank_k must be >= 0");
+    a.rerank = std::min(o.rerank_k > 0 ? o.rerank_k : K, L);
+  }
   const int lcap = 64 * preg;
   size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 +
                  (lc.query_in_regs ? 0 : (size_t)d * 4 * (dtype == SSG_FP8E4M3 ? 2 : 1));
@@ -681,6 +811,7 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
     if (n > SSG_EXACT_VISITED_MAX_N)
       return fail(SSG_EUNSUPPORTED, "exact visited set needs n <= %d", SSG_EXACT_VISITED_MAX_N);
     table = (size_t)((n + 31) / 32) * 4;
+    if (o.base_f32) table = std::max(table, (size_t)lcap * 8);
     a.hash_log2 = 0;
   } else {
     int hl = o.hash_log2 > 0 ? o.hash_log2 : 11;
@@ -701,6 +832,31 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   const int64_t blocks = (nq + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return fail(SSG_EINVAL, "too many queries");
   hipLaunchKernelGGL(lc.fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_quantize(const float* base_f32, int64_t n, int32_t d, int32_t dtype, float* dim_scale,
+                 void* out, void* stream) {
+  if (!base_f32 || !out || n < 1 || d < 1) return fail(SSG_EINVAL, "bad quantize arguments");
+  if (dtype != SSG_BF16 && dtype != SSG_FP8E4M3)
+    return fail(SSG_EINVAL, "quantize supports SSG_BF16 and SSG_FP8E4M3");
+  if (dtype == SSG_FP8E4M3 && !dim_scale) return fail(SSG_EINVAL, "FP8 needs dim_scale");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == SSG_FP8E4M3) {
+    uint32_t* cm = reinterpret_cast<uint32_t*>(dim_scale);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((d + 255) / 256), dim3(256), 0, st, cm, 0u, (int64_t)d);
+    const int rows = (int)std::min<int64_t>(n, 2048);
+    hipLaunchKernelGGL(absmax_cols_kernel, dim3(rows, (d + 255) / 256), dim3(256), 0, st, base_f32,
+                       n, d, cm);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3((d + 255) / 256), dim3(256), 0, st, dim_scale, d);
+  }
+  const int64_t total = n * (int64_t)d;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(encode_kernel, dim3(blocks), dim3(256), 0, st, base_f32, n, d, dtype,
+                     dim_scale, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
   g_err.clear();

@@ -1,7 +1,9 @@
 """Loader of NSSG graph caches into HBM.
 
-A cache directory holds ``graph.npy`` (uint32 [n, R], rows of neighbour ids
-followed by 0xFFFFFFFF padding: the fixed-width n x m layout of Sec. 6.2),
+A cache directory holds the graph in compressed rows (``graph_off.npy``, int64
+[n+1], and ``graph_ids.npy``, uint32: row i is ids[off[i]:off[i+1]]), which the
+loader expands into the fixed-width n x R matrix the kernels read (ids, then
+0xFFFFFFFF padding: the n x m layout of Sec. 6.2),
 ``entry_ids.npy`` (uint32 [s], the navigating nodes) and ``meta.json`` (build
 parameters and checksums). Arrays are read with numpy's pickle-free loader.
 """
@@ -35,7 +37,16 @@ def load(name: str, root: str | None = None, verify: bool = True) -> dict:
         raise FileNotFoundError(f"graph cache {d} not found (built by the oracle's cache script)")
     with open(os.path.join(d, "meta.json")) as f:
         meta = json.load(f)
-    graph = np.load(os.path.join(d, "graph.npy"), allow_pickle=False)
+    off = np.load(os.path.join(d, "graph_off.npy"), allow_pickle=False)
+    ids = np.load(os.path.join(d, "graph_ids.npy"), allow_pickle=False)
+    R = int(meta["R"])
+    n = len(off) - 1
+    graph = np.full((n, R), 0xFFFFFFFF, np.uint32)
+    for_row = np.repeat(np.arange(n), np.diff(off))
+    slot = np.arange(len(ids)) - off[for_row]
+    if len(ids) and (slot.max() >= R or ids.max() >= n):
+        raise ValueError(f"corrupt graph rows in {d}")
+    graph[for_row, slot] = ids
     entry = np.load(os.path.join(d, "entry_ids.npy"), allow_pickle=False)
     if graph.dtype != np.uint32 or graph.ndim != 2:
         raise ValueError("graph must be a 2-D uint32 array")

@@ -8,8 +8,8 @@ every workload here is drawn from a seeded mixture with the same shape:
            base points reused as indexed queries.
 * ``c2``   1,000,000 x 128 integers 0..255 (SIFT-like), 1,000 overlapping
            rank-16 Gaussian clusters, clipped and rounded (LID about 13).
-* ``c3``   1,000,000 x 960 values in [0, 1] (GIST-like), 500 clusters whose
-           means are Dirichlet draws.
+* ``c3``   1,000,000 x 960 values in [0, 1] (GIST-like), 500 overlapping
+           rank-20 clusters around a Dirichlet-shaped mean profile (LID about 28).
 * ``c4``   1,000,000 x 96 unit-norm low-rank mixture (Deep-like), inner
            product, queries with per-query pool size L and result count K.
 * ``c5``   5,000,000 x 96, the c4 distribution, for the serving loop.
@@ -44,25 +44,26 @@ CONFIGS: dict[str, dict] = {
     "c2s": dict(kind="gmm_int", n=20_000, d=128, comps=40, rank=16,
                 nq_unindexed=500, nq_indexed=12, knn_k=100, l=100, R=50,
                 alpha=60.0, s=10, L=64, K=100, metric="l2", seed=2100),
-    "c3": dict(kind="dirichlet", n=1_000_000, d=960, comps=500, rank=30,
+    "c3": dict(kind="dirichlet", n=1_000_000, d=960, comps=500, rank=20, eps=0.003,
                nq_unindexed=1_000, nq_indexed=0, knn_k=100, l=500, R=50,
                alpha=60.0, s=10, L=200, K=10, L_sweep=list(range(100, 401, 50)),
                metric="l2", seed=3000),
-    "c3s": dict(kind="dirichlet", n=8_000, d=960, comps=20, rank=30,
+    "c3s": dict(kind="dirichlet", n=8_000, d=960, comps=20, rank=20, eps=0.003,
                 nq_unindexed=100, nq_indexed=4, knn_k=60, l=120, R=50,
                 alpha=60.0, s=10, L=100, K=10, metric="l2", seed=3100),
-    "c4": dict(kind="unit_lowrank", n=1_000_000, d=96, comps=1000, rank=10,
+    "c4": dict(kind="unit_lowrank", n=1_000_000, d=96, comps=1000, rank=16,
                nq_unindexed=100_000, nq_indexed=0, knn_k=100, l=100, R=50,
                alpha=60.0, s=10, L=128, K=10, metric="ip", seed=4000,
                L_choices=list(range(16, 513, 16)), K_choices=[1, 10, 100]),
-    "c4s": dict(kind="unit_lowrank", n=20_000, d=96, comps=40, rank=10,
+    "c4s": dict(kind="unit_lowrank", n=20_000, d=96, comps=40, rank=16,
                 nq_unindexed=2_000, nq_indexed=0, knn_k=60, l=100, R=50,
                 alpha=60.0, s=10, L=128, K=10, metric="ip", seed=4100,
                 L_choices=list(range(16, 513, 16)), K_choices=[1, 10, 100]),
-    "c5": dict(kind="unit_lowrank", n=5_000_000, d=96, comps=5000, rank=10,
+    "c5": dict(kind="unit_lowrank", n=5_000_000, d=96, comps=5000, rank=16,
                nq_unindexed=95_000, nq_indexed=5_000, knn_k=64, l=100, R=32,
                alpha=60.0, s=10, L=96, K=10, metric="ip", seed=5000,
-               L_choices=list(range(32, 257, 16)), K_choices=[10]),
+               L_choices=list(range(32, 257, 16)), K_choices=[10],
+               knn="ivf", nlist=5000, nprobe=24, refine_J=32, refine_rounds=3),
 }
 
 
@@ -86,8 +87,12 @@ def _params(cfg: dict):
         U = rng.normal(0.0, 6.0, (k, d, cfg["rank"]))
         return rng, dict(mu=mu, U=U)
     if kind == "dirichlet":
-        mu = rng.dirichlet(np.full(d, 0.5), size=k) * (d * 0.15)
-        V = rng.normal(0.0, 0.03, (k, d, cfg["rank"]))
+        # one skewed Dirichlet-shaped mean profile shared by all clusters, small
+        # per-cluster offsets and low-rank in-cluster spread: overlapping
+        # clusters in [0, 1] with a high intrinsic dimension, like GIST1M
+        m = cfg.get("floor", 0.05) + rng.dirichlet(np.full(d, 0.5)) * (d * 0.1)
+        mu = m[None, :] + rng.normal(0.0, cfg.get("c_off", 0.02), (k, d))
+        V = rng.normal(0.0, cfg.get("u_std", 0.03), (k, d, cfg["rank"]))
         return rng, dict(mu=mu, U=V)
     if kind == "unit_lowrank":
         mu = rng.standard_normal((k, d))
@@ -117,7 +122,7 @@ def _draw(cfg: dict, p: dict, rng: np.random.Generator, m: int) -> np.ndarray:
                 x += rng.normal(0.0, 1.0, (c, d))
                 x = np.rint(np.clip(x, 0.0, 255.0))
             elif kind == "dirichlet":
-                x += rng.normal(0.0, 0.01, (c, d))
+                x += rng.normal(0.0, cfg.get("eps", 0.01), (c, d))
                 x = np.clip(x, 0.0, 1.0)
             else:  # unit_lowrank
                 x += rng.normal(0.0, 0.05, (c, d))
