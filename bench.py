@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the index and every query "
@@ -177,9 +178,70 @@ def main():
                      "gpu_ndc_mean": float(gndc.mean())},
         "kernel_source": source_digest(),
     }
+    if not a.no_forms:
+        out["forms"] = precision_forms(tb, tg, te, tq, K, L, gt, sweep, cfg, a, launch_ms)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(base, gc, q, K, L, cfg, a.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def _time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
+    """BF16 and FP8-E4M3 storage (FP32 accumulation, FP32 rerank of the whole
+    pool) on the same workload: for each form the smallest swept L whose GPU
+    recall@10 is >= 0.95, and its throughput, against the FP32 search."""
+    import torch
+
+    from paper_1907_06146_amd import quantize, search
+
+    stream = torch.cuda.current_stream()
+    nq = tq.shape[0]
+    d = tb.shape[1]
+    forms = {"fp32": {"L": L_fp32, "ms_per_step": fp32_ms, "qps": nq / fp32_ms * 1e3}}
+    Ls = sorted(set(sweep_Ls(sweep)) | {L_fp32})
+    for fmt in ("bf16", "fp8"):
+        codes, scale = quantize(tb, fmt)
+        torch.cuda.synchronize()
+        best = None
+        for L in [x for x in Ls if x >= min(Ls)]:
+            kw = dict(dim_scale=scale, base_f32=tb, rerank_k=L)
+            ids, _ = search(codes, tg, te, tq, K, L, **kw)
+            torch.cuda.synchronize()
+            r10 = recall_at(ids.cpu().numpy(), gt, 10)
+            if r10 >= 0.95:
+                ms = _time(lambda: search(codes, tg, te, tq, K, L, **kw), a.steps, 2, stream)
+                _, _, ndc, hops = search(codes, tg, te, tq, K, L, stats=True, **kw)
+                ndc = ndc.double().mean().item()
+                hops = hops.double().mean().item()
+                eb = 2 if fmt == "bf16" else 1
+                bq = 4 * d + cfg["s"] * d * eb + hops * 4 * tg.shape[1] + (ndc - cfg["s"]) * d * eb \
+                    + min(L, K) * d * 4 + 8 * K
+                best = {"L": L, "recall10": r10, "ms_per_step": ms, "qps": nq / ms * 1e3,
+                        "speedup_vs_fp32": fp32_ms / ms, "gpu_ndc_mean": ndc,
+                        "bytes_per_query": bq, "achieved_GBps": bq * nq / (ms / 1e3) / 1e9,
+                        "rerank": "fp32, whole pool"}
+                break
+        forms[fmt] = best
+        log(f"form {fmt}: {best}")
+    return forms
+
+
+def sweep_Ls(sweep):
+    return [r["L"] for r in sweep["rows"]]
 
 
 def cpu_baseline(base, gc, q, K, L, cfg, sample):
