@@ -129,6 +129,72 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
 int ssg_quantize(const float* base_f32, int64_t n, int32_t d, int32_t dtype, float* dim_scale,
                  void* out, void* stream);
 
+/* ------------------------------------------------------------------ batched
+ * Mixed-workload form: queries with their own pool size L_i and result count
+ * K_i, split into buckets of similar L (each bucket sizes its on-chip pool for
+ * its largest L). Each bucket runs as a persistent kernel whose wavefronts
+ * take query slots from a device work queue until it is exhausted, so long
+ * and short searches balance across the GPU. Not from the paper, whose
+ * search is one query per CPU thread; every query computes exactly Alg. 1
+ * with its own L_i and K_i.
+ */
+typedef struct {
+    const void* base;          /* DEVICE n x d, as in ssg_search */
+    int64_t n;
+    int32_t d, dtype, metric;
+    const float* dim_scale;    /* DEVICE float[d] for FP8, else NULL */
+    const float* base_f32;     /* DEVICE FP32 vectors for the rerank, or NULL */
+    int32_t rerank;            /* 0: none; -1: rerank the first K_i entries of
+                                  each query; > 0: that many (capped at L_i) */
+    const uint32_t* graph;     /* DEVICE n x R */
+    int32_t R;
+    const uint32_t* entry_ids; /* DEVICE [n_entry] */
+    int32_t n_entry;
+    const float* queries;      /* DEVICE nq x d FP32 */
+    int64_t nq;
+    const int32_t* L;          /* DEVICE int32[nq], each 1..SSG_L_MAX */
+    const int32_t* K;          /* DEVICE int32[nq], each 1..kstride */
+    int32_t kstride;           /* output row stride (>= every K_i, <= SSG_K_MAX) */
+    uint32_t* out_ids;         /* DEVICE nq x kstride; row i: K_i results, then
+                                  SSG_SENTINEL padding */
+    float* out_dists;          /* DEVICE nq x kstride (+inf padding) */
+    int32_t* out_ndc;          /* DEVICE int32[nq] or NULL */
+    int32_t* out_hops;         /* DEVICE int32[nq] or NULL */
+} ssg_batch_desc;
+
+typedef struct {
+    const int32_t* qlist;      /* DEVICE int32[count]: query indices of this bucket
+                                  (processed in this order: put long searches first) */
+    int64_t count;
+    int32_t max_L;             /* >= every L_i of the bucket; sizes the pool */
+    int32_t gather_variant;    /* launch shape (see ssg_search_opts); 0 = default */
+    int32_t hash_log2;         /* 0 = default */
+    int32_t waves_per_block;   /* 0 = default */
+    int32_t blocks;            /* persistent grid size; 0 = fill the GPU once */
+} ssg_bucket;
+
+/* Workspace for nb buckets (one work-queue counter each). */
+size_t ssg_batch_workspace_bytes(int32_t nb);
+
+/* Enqueue every bucket on `stream`, one after another (counters are reset by
+ * a kernel first). The caller must not free the descriptor's arrays before
+ * the work completes; the descriptor structs themselves may be freed on
+ * return. Returns SSG_OK or a negative status. */
+int ssg_search_batched(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* A captured HIP graph of the same work with the buckets on parallel graph
+ * branches, replayed by ssg_batch_graph_launch as one launch. The device
+ * arrays named by the descriptor are baked into the graph: keep them alive
+ * and in place until ssg_batch_graph_destroy; their contents may change
+ * between launches. */
+typedef struct ssg_batch_graph ssg_batch_graph;
+int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
+                           const ssg_bucket* buckets, int32_t nb, void* workspace,
+                           size_t workspace_bytes);
+int ssg_batch_graph_launch(ssg_batch_graph* g, void* stream);
+int ssg_batch_graph_destroy(ssg_batch_graph* g);
+
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
 

@@ -21,7 +21,9 @@ SENTINEL = 0xFFFFFFFF
 L_MAX, R_MAX, K_MAX = 512, 64, 4096
 
 EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_bytes",
-           "ssg_validate_graph", "ssg_last_error", "ssg_version")
+           "ssg_validate_graph", "ssg_last_error", "ssg_version", "ssg_batch_workspace_bytes",
+           "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
+           "ssg_batch_graph_destroy")
 
 
 class SSGError(RuntimeError):
@@ -35,6 +37,24 @@ class SearchOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
                 ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
                 ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("dim_scale", ctypes.c_void_p), ("base_f32", ctypes.c_void_p),
+                ("rerank", ctypes.c_int32), ("graph", ctypes.c_void_p), ("R", ctypes.c_int32),
+                ("entry_ids", ctypes.c_void_p), ("n_entry", ctypes.c_int32),
+                ("queries", ctypes.c_void_p), ("nq", ctypes.c_int64), ("L", ctypes.c_void_p),
+                ("K", ctypes.c_void_p), ("kstride", ctypes.c_int32), ("out_ids", ctypes.c_void_p),
+                ("out_dists", ctypes.c_void_p), ("out_ndc", ctypes.c_void_p),
+                ("out_hops", ctypes.c_void_p)]
+
+
+class Bucket(ctypes.Structure):
+    _fields_ = [("qlist", ctypes.c_void_p), ("count", ctypes.c_int64), ("max_L", ctypes.c_int32),
+                ("gather_variant", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -62,6 +82,18 @@ def lib() -> ctypes.CDLL:
             L.ssg_search_workspace_bytes.restype = sz
             L.ssg_validate_graph.argtypes = [P, i64, i32]
             L.ssg_validate_graph.restype = ctypes.c_int
+            L.ssg_batch_workspace_bytes.argtypes = [i32]
+            L.ssg_batch_workspace_bytes.restype = sz
+            L.ssg_search_batched.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(Bucket), i32, P,
+                                             sz, P]
+            L.ssg_search_batched.restype = ctypes.c_int
+            L.ssg_batch_graph_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(BatchDesc),
+                                                 ctypes.POINTER(Bucket), i32, P, sz]
+            L.ssg_batch_graph_create.restype = ctypes.c_int
+            L.ssg_batch_graph_launch.argtypes = [P, P]
+            L.ssg_batch_graph_launch.restype = ctypes.c_int
+            L.ssg_batch_graph_destroy.argtypes = [P]
+            L.ssg_batch_graph_destroy.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

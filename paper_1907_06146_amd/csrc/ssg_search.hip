@@ -40,7 +40,9 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "ssg.h"
 
@@ -157,7 +159,14 @@ struct Args {
   int32_t hash_log2;   // hash mode: log2 table size
   int32_t lds_per_wave;
   const float* base_f32;  // FP32 vectors for the final rerank, or null
-  int32_t rerank;         // pool entries to rerank (<= 64 * PREG)
+  int32_t rerank;         // pool entries to rerank (<= 64 * PREG); -1: K of each query
+  // batched / persistent mode
+  const int32_t* qlist;   // query indices processed by this launch, or null (0..nlist)
+  int64_t nlist;          // number of entries of qlist (or queries)
+  const int32_t* L_arr;   // per-query pool size, or null (L)
+  const int32_t* K_arr;   // per-query result count, or null (K)
+  int32_t kstride;        // output row stride (>= every K)
+  uint32_t* counter;      // persistent work queue head, or null (one query per wave)
 };
 
 // ------------------------------------------------------------------ kernel
@@ -166,8 +175,8 @@ struct Args {
 // all issued before the first is consumed (NP * 64 / G candidates in flight);
 // PREG: pool registers per lane (pool capacity 64 * PREG).
 template <typename T, int DC, int G, int NP, int PREG>
-__global__ __launch_bounds__(256) void search_kernel(Args a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void run_query(const Args& a, unsigned char* my, const int lane,
+                                          const int64_t qid, const int L, const int K) {
   constexpr int EPC = T::kEpc;
   constexpr int CPP = 64 / G;                           // candidates per pass
   constexpr int NCH = DC > 0 ? (DC + G - 1) / G : 1;    // chunks per lane
@@ -175,12 +184,6 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   constexpr bool kQueryInRegs = DC > 0;
   constexpr bool kScaled = T::kScaled;
 
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t qid = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
-  if (qid >= a.nq) return;  // uniform per wavefront
-
-  unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
   uint64_t* stage = reinterpret_cast<uint64_t*>(my);
   uint64_t* bkeys = stage + LCAP;
   uint32_t* bids = reinterpret_cast<uint32_t*>(bkeys + 64);
@@ -192,7 +195,6 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   const int grp = lane / G;
   const float* q = a.queries + (size_t)qid * a.d;
   const bool ip = a.metric == 1;
-  const int L = a.L;
   const int R = a.R;
 
   // query (and fp8 scale) fragment: lane g holds chunks g, g+G, ...
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   // against the FP32 vectors, re-sorted by (dist, id). The visited table is
   // dead here, so its LDS holds the new keys; `stage` holds the sorted order.
   if (a.base_f32 != nullptr) {
-    const int rr = min(a.rerank, size);
+    const int rr = min(a.rerank < 0 ? K : a.rerank, size);
     uint32_t* rids = bids;  // reused 64 at a time
     uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
     const int d4 = a.d >> 2;
@@ -509,25 +511,65 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
     wave_sync();
   }
 
-  // ---- output: first K pool entries, padded
-  uint32_t* oid = a.out_ids + (size_t)qid * a.K;
-  float* od = a.out_d + (size_t)qid * a.K;
+  // ---- output: first K pool entries, padded to the row stride
+  uint32_t* oid = a.out_ids + (size_t)qid * a.kstride;
+  float* od = a.out_d + (size_t)qid * a.kstride;
 #pragma unroll
   for (int k = 0; k < PREG; ++k) {
     const int i = k * 64 + lane;
-    if (i < a.K) {
-      const uint64_t key = pool[k];
+    if (i < a.kstride) {
+      const uint64_t key = i < K ? pool[k] : kNoKey;
       oid[i] = key == kNoKey ? kSent : key_id(key);
       od[i] = key == kNoKey ? __uint_as_float(0x7F800000u) : unord_f32((uint32_t)(key >> 32));
     }
   }
-  for (int i = LCAP + lane; i < a.K; i += 64) {
+  for (int i = LCAP + lane; i < a.kstride; i += 64) {
     oid[i] = kSent;
     od[i] = __uint_as_float(0x7F800000u);
   }
   if (lane == 0) {
     if (a.out_ndc) a.out_ndc[qid] = ndc;
     if (a.out_hops) a.out_hops[qid] = hops;
+  }
+  wave_sync();  // LDS of this wave is reused by its next query
+}
+
+// One query per wavefront (counter == null), or persistent: every wavefront
+// takes the next slot of the work queue until the queue is exhausted (each
+// wavefront exits once its fetched slot is past the end).
+template <typename T, int DC, int G, int NP, int PREG>
+__global__ __launch_bounds__(256) void search_kernel(Args a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
+  const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  if (slot >= a.nq) return;  // uniform per wavefront
+  run_query<T, DC, G, NP, PREG>(a, my, lane, slot, a.L, a.K);
+}
+
+template <typename T, int DC, int G, int NP, int PREG>
+__global__ __launch_bounds__(256) void search_kernel_batched(Args a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
+  int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  for (;;) {
+    if (a.counter) {
+      uint32_t s0 = 0u;
+      if (lane == 0) s0 = atomicAdd(a.counter, 1u);
+      slot = (int64_t)__builtin_amdgcn_readfirstlane(s0);
+    }
+    if (slot >= a.nlist) break;  // uniform per wavefront
+    const int64_t qid = a.qlist ? (int64_t)a.qlist[slot] : slot;
+    if (qid >= 0 && qid < a.nq) {  // a bad queue entry is skipped, never dereferenced
+      // per-query sizes are clamped to this launch's pool capacity and row stride
+      const int L = min(max(a.L_arr ? a.L_arr[qid] : a.L, 1), 64 * PREG);
+      const int K = min(max(a.K_arr ? a.K_arr[qid] : a.K, 1), a.kstride);
+      run_query<T, DC, G, NP, PREG>(a, my, lane, qid, L, K);
+    }
+    if (!a.counter) break;
   }
 }
 
@@ -619,7 +661,15 @@ struct Launch {
 };
 
 template <typename T, int DC, int G, int NP>
-KernelFn pick_preg(int preg) {
+KernelFn pick_preg(int preg, bool batched) {
+  if (batched) {
+    switch (preg) {
+      case 1: return search_kernel_batched<T, DC, G, NP, 1>;
+      case 2: return search_kernel_batched<T, DC, G, NP, 2>;
+      case 4: return search_kernel_batched<T, DC, G, NP, 4>;
+      default: return search_kernel_batched<T, DC, G, NP, 8>;
+    }
+  }
   switch (preg) {
     case 1: return search_kernel<T, DC, G, NP, 1>;
     case 2: return search_kernel<T, DC, G, NP, 2>;
@@ -638,56 +688,56 @@ template <typename T>
 struct Table;
 template <>
 struct Table<F32T> {
-  static Launch pick(int dc, int preg, int variant) {
+  static Launch pick(int dc, int preg, int variant, bool batched) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 8: l.fn = pick_preg<F32T, 8, 2, 1>(preg); return l;    // d = 32: 32 in flight
-      case 24: l.fn = pick_preg<F32T, 24, 4, 1>(preg); return l;  // d = 96: 16
-      case 25: l.fn = pick_preg<F32T, 25, 4, 1>(preg); return l;  // d = 100: 16
+      case 8: l.fn = pick_preg<F32T, 8, 2, 1>(preg, batched); return l;    // d = 32: 32 in flight
+      case 24: l.fn = pick_preg<F32T, 24, 4, 1>(preg, batched); return l;  // d = 96: 16
+      case 25: l.fn = pick_preg<F32T, 25, 4, 1>(preg, batched); return l;  // d = 100: 16
       case 32:                                                     // d = 128
         switch (variant) {
-          case 1: l.fn = pick_preg<F32T, 32, 8, 1>(preg); return l;  // 8 in flight
-          case 2: l.fn = pick_preg<F32T, 32, 8, 2>(preg); return l;  // 16
-          case 3: l.fn = pick_preg<F32T, 32, 4, 2>(preg); return l;  // 32
-          default: l.fn = pick_preg<F32T, 32, 4, 1>(preg); return l; // 16
+          case 1: l.fn = pick_preg<F32T, 32, 8, 1>(preg, batched); return l;  // 8 in flight
+          case 2: l.fn = pick_preg<F32T, 32, 8, 2>(preg, batched); return l;  // 16
+          case 3: l.fn = pick_preg<F32T, 32, 4, 2>(preg, batched); return l;  // 32
+          default: l.fn = pick_preg<F32T, 32, 4, 1>(preg, batched); return l; // 16
         }
-      case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg); return l;  // d = 300: 8
+      case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg, batched); return l;  // d = 300: 8
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<F32T, 0, 16, 2>(preg);
+    l.fn = pick_preg<F32T, 0, 16, 2>(preg, batched);
     return l;
   }
 };
 template <>
 struct Table<BF16T> {
-  static Launch pick(int dc, int preg, int variant) {
+  static Launch pick(int dc, int preg, int variant, bool batched) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 12: l.fn = pick_preg<BF16T, 12, 4, 1>(preg); return l;  // d = 96
+      case 12: l.fn = pick_preg<BF16T, 12, 4, 1>(preg, batched); return l;  // d = 96
       case 16:                                                      // d = 128
         switch (variant) {
-          case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg); return l;
-          default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg); return l;
+          case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg, batched); return l;
+          default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;
         }
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<BF16T, 0, 16, 2>(preg);
+    l.fn = pick_preg<BF16T, 0, 16, 2>(preg, batched);
     return l;
   }
 };
 template <>
 struct Table<FP8T> {
-  static Launch pick(int dc, int preg, int) {
+  static Launch pick(int dc, int preg, int, bool batched) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 6: l.fn = pick_preg<FP8T, 6, 4, 1>(preg); return l;  // d = 96
-      case 8: l.fn = pick_preg<FP8T, 8, 4, 1>(preg); return l;  // d = 128
+      case 6: l.fn = pick_preg<FP8T, 6, 4, 1>(preg, batched); return l;  // d = 96
+      case 8: l.fn = pick_preg<FP8T, 8, 4, 1>(preg, batched); return l;  // d = 128
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<FP8T, 0, 16, 2>(preg);
+    l.fn = pick_preg<FP8T, 0, 16, 2>(preg, batched);
     return l;
   }
 };
@@ -723,6 +773,38 @@ int check_common(const void* base, int64_t n, int32_t d, int32_t dtype, const fl
 }
 
 int preg_for(int L) { return L <= 64 ? 1 : L <= 128 ? 2 : L <= 256 ? 4 : 8; }
+
+Launch pick_launch(int dtype, int dc, int preg, int variant, bool batched) {
+  return dtype == SSG_F32    ? Table<F32T>::pick(dc, preg, variant, batched)
+         : dtype == SSG_BF16 ? Table<BF16T>::pick(dc, preg, variant, batched)
+                             : Table<FP8T>::pick(dc, preg, variant, batched);
+}
+
+// LDS bytes per wavefront and the hash size for a pool capacity of 64*preg.
+int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, bool exact, int64_t n,
+               bool rerank, int hash_log2_req, int* hash_log2_out, size_t* per_wave) {
+  const int lcap = 64 * preg;
+  size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 +
+                 (query_in_regs ? 0 : (size_t)d * 4 * (dtype == SSG_FP8E4M3 ? 2 : 1));
+  size_t table;
+  if (exact) {
+    if (n > SSG_EXACT_VISITED_MAX_N)
+      return fail(SSG_EUNSUPPORTED, "exact visited set needs n <= %d", SSG_EXACT_VISITED_MAX_N);
+    table = (size_t)((n + 31) / 32) * 4;
+    if (rerank) table = std::max(table, (size_t)lcap * 8);
+    *hash_log2_out = 0;
+  } else {
+    int hl = hash_log2_req > 0 ? hash_log2_req : 11;
+    // the table must hold the pool plus one row at load <= 1/2
+    while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
+    if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");
+    *hash_log2_out = hl;
+    table = (size_t)4 << hl;
+  }
+  *per_wave = (fixed + table + 15) & ~(size_t)15;
+  return SSG_OK;
+}
+
 
 }  // namespace
 
@@ -768,9 +850,7 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   const int preg = preg_for(L);
   const int epc = dtype == SSG_F32 ? 4 : dtype == SSG_BF16 ? 8 : 16;
   const int dc = d / epc;
-  Launch lc = dtype == SSG_F32    ? Table<F32T>::pick(dc, preg, o.gather_variant)
-              : dtype == SSG_BF16 ? Table<BF16T>::pick(dc, preg, o.gather_variant)
-                                  : Table<FP8T>::pick(dc, preg, o.gather_variant);
+  Launch lc = pick_launch(dtype, dc, preg, o.gather_variant, false);
   // one wavefront per workgroup measured fastest on the 1M x 128 workload
   // (finer-grained dispatch, no LDS fragmentation across waves)
   int wpb = o.waves_per_block > 0 ? o.waves_per_block : 1;
@@ -794,6 +874,12 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.out_d = out_dists;
   a.out_ndc = o.out_ndc;
   a.out_hops = o.out_hops;
+  a.qlist = nullptr;
+  a.nlist = nq;
+  a.L_arr = nullptr;
+  a.K_arr = nullptr;
+  a.kstride = K;
+  a.counter = nullptr;
   a.exact = o.exact_visited ? 1 : 0;
   a.base_f32 = o.base_f32;
   a.rerank = 0;
@@ -803,25 +889,10 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
     if (o.rerank_k < 0) return fail(SSG_EINVAL, "rerank_k must be >= 0");
     a.rerank = std::min(o.rerank_k > 0 ? o.rerank_k : K, L);
   }
-  const int lcap = 64 * preg;
-  size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 +
-                 (lc.query_in_regs ? 0 : (size_t)d * 4 * (dtype == SSG_FP8E4M3 ? 2 : 1));
-  size_t table;
-  if (a.exact) {
-    if (n > SSG_EXACT_VISITED_MAX_N)
-      return fail(SSG_EUNSUPPORTED, "exact visited set needs n <= %d", SSG_EXACT_VISITED_MAX_N);
-    table = (size_t)((n + 31) / 32) * 4;
-    if (o.base_f32) table = std::max(table, (size_t)lcap * 8);
-    a.hash_log2 = 0;
-  } else {
-    int hl = o.hash_log2 > 0 ? o.hash_log2 : 11;
-    // the table must hold the pool plus one row at load <= 1/2
-    while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
-    if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");
-    a.hash_log2 = hl;
-    table = (size_t)4 << hl;
-  }
-  size_t per_wave = (fixed + table + 15) & ~(size_t)15;
+  size_t per_wave = 0;
+  rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, a.exact != 0, n, o.base_f32 != nullptr,
+                  o.hash_log2, &a.hash_log2, &per_wave);
+  if (rc) return rc;
   if (per_wave * wpb > 64 * 1024) {
     wpb = (int)((64 * 1024) / per_wave);
     if (wpb < 1) return fail(SSG_EUNSUPPORTED, "per-query LDS need %zu exceeds the CU", per_wave);
@@ -859,6 +930,209 @@ int ssg_quantize(const float* base_f32, int64_t n, int32_t d, int32_t dtype, flo
                      dim_scale, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BucketLaunch {
+  KernelFn fn;
+  Args a;
+  unsigned blocks;
+  unsigned threads;
+  size_t lds;
+  uint32_t* counter;
+};
+
+int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* ws, size_t wsb,
+                    std::vector<BucketLaunch>& out) {
+  if (!D || !B) return fail(SSG_EINVAL, "descriptor or buckets is NULL");
+  if (nb < 1 || nb > 64) return fail(SSG_EINVAL, "nb must be in [1, 64] (got %d)", nb);
+  if (!ws || wsb < ssg_batch_workspace_bytes(nb) || reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(SSG_ENOMEM, "workspace must be 256-byte aligned and hold %zu bytes",
+                ssg_batch_workspace_bytes(nb));
+  int maxL = 1;
+  for (int i = 0; i < nb; ++i) maxL = std::max(maxL, B[i].max_L);
+  int rc = check_common(D->base, D->n, D->d, D->dtype, D->dim_scale, D->graph, D->R, D->entry_ids,
+                        D->n_entry, D->queries, D->nq, D->kstride, maxL, D->metric, D->out_ids,
+                        D->out_dists);
+  if (rc) return rc;
+  if (D->nq > 0 && (!D->L || !D->K)) return fail(SSG_EINVAL, "per-query L and K arrays are required");
+  if (D->rerank < -1) return fail(SSG_EINVAL, "rerank must be -1, 0 or positive");
+  if (D->rerank != 0 && !D->base_f32) return fail(SSG_EINVAL, "rerank needs base_f32");
+  if (D->base_f32 && reinterpret_cast<uintptr_t>(D->base_f32) % 16)
+    return fail(SSG_EINVAL, "base_f32 must be 16-byte aligned");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(SSG_EDEVICE, "cannot query the device");
+  const int epc = D->dtype == SSG_F32 ? 4 : D->dtype == SSG_BF16 ? 8 : 16;
+  const int dc = D->d / epc;
+  out.clear();
+  for (int i = 0; i < nb; ++i) {
+    const ssg_bucket& b = B[i];
+    if (b.count < 0 || (b.count > 0 && !b.qlist)) return fail(SSG_EINVAL, "bucket %d: bad query list", i);
+    if (b.max_L < 1 || b.max_L > SSG_L_MAX) return fail(SSG_EUNSUPPORTED, "bucket %d: max_L %d", i, b.max_L);
+    if (b.waves_per_block < 0 || b.waves_per_block > 4 || b.blocks < 0)
+      return fail(SSG_EINVAL, "bucket %d: bad launch shape", i);
+    const int preg = preg_for(b.max_L);
+    Launch lc = pick_launch(D->dtype, dc, preg, b.gather_variant, true);
+    BucketLaunch bl{};
+    Args& a = bl.a;
+    size_t per_wave = 0;
+    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, false, D->n, D->base_f32 != nullptr,
+                    b.hash_log2, &a.hash_log2, &per_wave);
+    if (rc) return rc;
+    int wpb = b.waves_per_block > 0 ? b.waves_per_block : 1;
+    while (wpb > 1 && per_wave * wpb > 64 * 1024) --wpb;
+    if (per_wave > 64 * 1024) return fail(SSG_EUNSUPPORTED, "bucket %d: LDS need too large", i);
+    a.base = static_cast<const unsigned char*>(D->base);
+    a.n = D->n;
+    a.d = D->d;
+    a.dc = dc;
+    a.dim_scale = D->dtype == SSG_FP8E4M3 ? D->dim_scale : nullptr;
+    a.graph = D->graph;
+    a.R = D->R;
+    a.entry = D->entry_ids;
+    a.s = D->n_entry;
+    a.queries = D->queries;
+    a.nq = D->nq;
+    a.K = D->kstride;
+    a.L = b.max_L;
+    a.metric = D->metric;
+    a.out_ids = D->out_ids;
+    a.out_d = D->out_dists;
+    a.out_ndc = D->out_ndc;
+    a.out_hops = D->out_hops;
+    a.exact = 0;
+    a.lds_per_wave = (int)per_wave;
+    a.base_f32 = D->rerank != 0 ? D->base_f32 : nullptr;
+    a.rerank = D->rerank;
+    a.qlist = b.qlist;
+    a.nlist = b.count;
+    a.L_arr = D->L;
+    a.K_arr = D->K;
+    a.kstride = D->kstride;
+    bl.counter = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(ws) + (size_t)i * 256);
+    a.counter = bl.counter;
+    bl.fn = lc.fn;
+    bl.threads = 64u * wpb;
+    bl.lds = per_wave * wpb;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(lc.fn),
+                                                     (int)bl.threads, bl.lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    int64_t want = b.blocks > 0 ? b.blocks : (int64_t)per_cu * cus;
+    const int64_t need = (b.count + wpb - 1) / wpb;
+    bl.blocks = (unsigned)std::max<int64_t>(1, std::min(want, std::max<int64_t>(need, 1)));
+    out.push_back(bl);
+  }
+  return SSG_OK;
+}
+
+void enqueue_bucket(const BucketLaunch& bl, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, bl.counter, 0u, (int64_t)1);
+  hipLaunchKernelGGL(bl.fn, dim3(bl.blocks), dim3(bl.threads), bl.lds, st, bl.a);
+}
+
+}  // namespace
+
+struct ssg_batch_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+size_t ssg_batch_workspace_bytes(int32_t nb) { return (size_t)std::max(nb, 0) * 256; }
+
+int ssg_search_batched(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  std::vector<BucketLaunch> bl;
+  int rc = prepare_batched(desc, buckets, nb, workspace, workspace_bytes, bl);
+  if (rc) return rc;
+  if (desc->nq == 0) { g_err.clear(); return SSG_OK; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (const auto& b : bl) enqueue_bucket(b, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
+                           const ssg_bucket* buckets, int32_t nb, void* workspace,
+                           size_t workspace_bytes) {
+  if (!out) return fail(SSG_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::vector<BucketLaunch> bl;
+  int rc = prepare_batched(desc, buckets, nb, workspace, workspace_bytes, bl);
+  if (rc) return rc;
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> br(nb, nullptr);
+  std::vector<hipEvent_t> join(nb, nullptr);
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipEventRecord(fork, cap);
+    for (int i = 0; i < nb; ++i) {
+      hipStreamWaitEvent(br[i], fork, 0);
+      if (desc->nq > 0) enqueue_bucket(bl[i], br[i]);
+      hipEventRecord(join[i], br[i]);
+      hipStreamWaitEvent(cap, join[i], 0);
+    }
+    hipError_t le = hipGetLastError();
+    e = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess && le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int i = 0; i < nb; ++i) {
+    if (join[i]) hipEventDestroy(join[i]);
+    if (br[i]) hipStreamDestroy(br[i]);
+  }
+  if (fork) hipEventDestroy(fork);
+  if (cap) hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    return fail(SSG_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  auto* g = new (std::nothrow) ssg_batch_graph;
+  if (!g) {
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    return fail(SSG_ENOMEM, "out of host memory");
+  }
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_batch_graph_launch(ssg_batch_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(SSG_EINVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_batch_graph_destroy(ssg_batch_graph* g) {
+  if (!g) return SSG_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
   g_err.clear();
   return SSG_OK;
 }
