@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: 3 launches of the timed configuration, then a 1 GiB "
+                         "element-wise copy whose bytes calibrate the counters; no output")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the index and every query "
@@ -121,6 +124,17 @@ def main():
     kw = dict(out=(ids, dd), waves_per_block=a.waves_per_block, hash_log2=a.hash_log2,
               gather_variant=a.variant)
     stream = torch.cuda.current_stream(dev)
+
+    if a.pmc_probe:
+        for _ in range(3):
+            search(tb, tg, te, tq, K, L, **kw)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        log("pmc probe done: 3 search launches, 1 GiB copy")
+        return
 
     for _ in range(a.warmup):
         search(tb, tg, te, tq, K, L, **kw)

@@ -138,6 +138,25 @@ struct FP8T {
   }
 };
 
+// The same E4M3 decode through gfx950's packed conversion instruction (two
+// codes per instruction instead of a dozen integer operations per code).
+struct FP8HwT {
+  static constexpr int kEpc = 16;
+  static constexpr bool kScaled = true;
+  __device__ static __forceinline__ void decode(uint4 c, float* x) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+      x[4 * i] = lo[0];
+      x[4 * i + 1] = lo[1];
+      x[4 * i + 2] = hi[0];
+      x[4 * i + 3] = hi[1];
+    }
+  }
+};
+
 struct Args {
   const unsigned char* base;  // n x (DC * 16) bytes
   int64_t n;
@@ -174,14 +193,15 @@ struct Args {
 // G: lanes cooperating on one candidate; NP: gather passes whose loads are
 // all issued before the first is consumed (NP * 64 / G candidates in flight);
 // PREG: pool registers per lane (pool capacity 64 * PREG).
-template <typename T, int DC, int G, int NP, int PREG>
+template <typename T, int DC, int G, int NP, int PREG, bool QL>
 __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, const int lane,
                                           const int64_t qid, const int L, const int K) {
   constexpr int EPC = T::kEpc;
   constexpr int CPP = 64 / G;                           // candidates per pass
   constexpr int NCH = DC > 0 ? (DC + G - 1) / G : 1;    // chunks per lane
   constexpr int LCAP = 64 * PREG;
-  constexpr bool kQueryInRegs = DC > 0;
+  constexpr bool kCompiled = DC > 0;              // chunk count known at compile time
+  constexpr bool kQueryInRegs = kCompiled && !QL;  // else the query (and scale) sit in LDS
   constexpr bool kScaled = T::kScaled;
 
   uint64_t* stage = reinterpret_cast<uint64_t*>(my);
@@ -259,7 +279,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       float acc[NP];
 #pragma unroll
       for (int p = 0; p < NP; ++p) acc[p] = 0.f;
-      if constexpr (kQueryInRegs) {
+      if constexpr (kCompiled) {
         uint4 buf[NP][NCH];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -281,8 +301,16 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
               T::decode(buf[p][t], x);
 #pragma unroll
               for (int e = 0; e < EPC; ++e) {
-                const float xv = kScaled ? __fmul_rn(x[e], sf[t * EPC + e]) : x[e];
-                acc[p] = term(acc[p], qf[t * EPC + e], xv);
+                float sv, qv;
+                if constexpr (kQueryInRegs) {
+                  sv = kScaled ? sf[t * EPC + e] : 1.f;
+                  qv = qf[t * EPC + e];
+                } else {
+                  sv = kScaled ? qlds[a.d + ch * EPC + e] : 1.f;
+                  qv = qlds[ch * EPC + e];
+                }
+                const float xv = kScaled ? __fmul_rn(x[e], sv) : x[e];
+                acc[p] = term(acc[p], qv, xv);
               }
             }
           }
@@ -393,7 +421,17 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     if (m > 0) {
       batch_keys(m);
       b = lane < m ? bkeys[lane] : kNoKey;
+      if (size == L) {
+        // a new key above the L-th pool key would land at position >= L and be
+        // cut at once; drop it before the merge (it stays visited)
+        uint64_t worst = kNoKey;
+#pragma unroll
+        for (int k = 0; k < PREG; ++k)
+          if (k == ((L - 1) >> 6)) worst = readlane64(pool[k], (L - 1) & 63);
+        if (b > worst) b = kNoKey;
+      }
     }
+    const uint64_t bm = __ballot(b != kNoKey);  // new keys that can enter the pool
 
     // next expansion, decided before the merge so its row read overlaps it:
     // the smallest unchecked key u of (pool + new keys) is kept iff fewer
@@ -418,13 +456,14 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       nb_next = lane < R ? a.graph[(size_t)p * R + lane] : kSent;
     }
 
-    // rank-based merge of the m new keys into the pool, truncated to L
-    if (m > 0) {
+    // rank-based merge of the surviving new keys into the pool, truncated to L
+    if (bm) {
       int rank = 0, qcnt = 0;
       int shift[PREG];
 #pragma unroll
       for (int k = 0; k < PREG; ++k) shift[k] = 0;
-      for (int j = 0; j < m; ++j) {
+      for (uint64_t mm = bm; mm; mm &= mm - 1) {
+        const int j = __builtin_ctzll(mm);
         const uint64_t bj = readlane64(b, j);
         int r = 0;
 #pragma unroll
@@ -440,9 +479,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
         const int np = k * 64 + lane + shift[k];
         if (pool[k] != kNoKey && np < L) stage[np] = pool[k];
       }
-      if (lane < m && rank + qcnt < L) stage[rank + qcnt] = b;
+      if (b != kNoKey && rank + qcnt < L) stage[rank + qcnt] = b;
       wave_sync();
-      size = min(L, size + m);
+      size = min(L, size + __popcll(bm));
 #pragma unroll
       for (int k = 0; k < PREG; ++k) {
         const int i = k * 64 + lane;
@@ -537,7 +576,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
 // One query per wavefront (counter == null), or persistent: every wavefront
 // takes the next slot of the work queue until the queue is exhausted (each
 // wavefront exits once its fetched slot is past the end).
-template <typename T, int DC, int G, int NP, int PREG>
+template <typename T, int DC, int G, int NP, int PREG, bool QL>
 __global__ __launch_bounds__(256) void search_kernel(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -545,10 +584,10 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
   const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
   if (slot >= a.nq) return;  // uniform per wavefront
-  run_query<T, DC, G, NP, PREG>(a, my, lane, slot, a.L, a.K);
+  run_query<T, DC, G, NP, PREG, QL>(a, my, lane, slot, a.L, a.K);
 }
 
-template <typename T, int DC, int G, int NP, int PREG>
+template <typename T, int DC, int G, int NP, int PREG, bool QL>
 __global__ __launch_bounds__(256) void search_kernel_batched(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -567,7 +606,7 @@ __global__ __launch_bounds__(256) void search_kernel_batched(Args a) {
       // per-query sizes are clamped to this launch's pool capacity and row stride
       const int L = min(max(a.L_arr ? a.L_arr[qid] : a.L, 1), 64 * PREG);
       const int K = min(max(a.K_arr ? a.K_arr[qid] : a.K, 1), a.kstride);
-      run_query<T, DC, G, NP, PREG>(a, my, lane, qid, L, K);
+      run_query<T, DC, G, NP, PREG, QL>(a, my, lane, qid, L, K);
     }
     if (!a.counter) break;
   }
@@ -660,21 +699,21 @@ struct Launch {
   bool query_in_regs = false;
 };
 
-template <typename T, int DC, int G, int NP>
+template <typename T, int DC, int G, int NP, bool QL = false>
 KernelFn pick_preg(int preg, bool batched) {
   if (batched) {
     switch (preg) {
-      case 1: return search_kernel_batched<T, DC, G, NP, 1>;
-      case 2: return search_kernel_batched<T, DC, G, NP, 2>;
-      case 4: return search_kernel_batched<T, DC, G, NP, 4>;
-      default: return search_kernel_batched<T, DC, G, NP, 8>;
+      case 1: return search_kernel_batched<T, DC, G, NP, 1, QL>;
+      case 2: return search_kernel_batched<T, DC, G, NP, 2, QL>;
+      case 4: return search_kernel_batched<T, DC, G, NP, 4, QL>;
+      default: return search_kernel_batched<T, DC, G, NP, 8, QL>;
     }
   }
   switch (preg) {
-    case 1: return search_kernel<T, DC, G, NP, 1>;
-    case 2: return search_kernel<T, DC, G, NP, 2>;
-    case 4: return search_kernel<T, DC, G, NP, 4>;
-    default: return search_kernel<T, DC, G, NP, 8>;
+    case 1: return search_kernel<T, DC, G, NP, 1, QL>;
+    case 2: return search_kernel<T, DC, G, NP, 2, QL>;
+    case 4: return search_kernel<T, DC, G, NP, 4, QL>;
+    default: return search_kernel<T, DC, G, NP, 8, QL>;
   }
 }
 
@@ -699,6 +738,9 @@ struct Table<F32T> {
           case 1: l.fn = pick_preg<F32T, 32, 8, 1>(preg, batched); return l;  // 8 in flight
           case 2: l.fn = pick_preg<F32T, 32, 8, 2>(preg, batched); return l;  // 16
           case 3: l.fn = pick_preg<F32T, 32, 4, 2>(preg, batched); return l;  // 32
+          case 4: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 4, 1, true>(preg, batched); return l;
+          case 5: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 4, 2, true>(preg, batched); return l;
+          case 6: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 8, 2, true>(preg, batched); return l;
           default: l.fn = pick_preg<F32T, 32, 4, 1>(preg, batched); return l; // 16
         }
       case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg, batched); return l;  // d = 300: 8
@@ -714,10 +756,13 @@ struct Table<BF16T> {
   static Launch pick(int dc, int preg, int variant, bool batched) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 12: l.fn = pick_preg<BF16T, 12, 4, 1>(preg, batched); return l;  // d = 96
+      case 12:                                                             // d = 96
+        if (variant == 4) { l.query_in_regs = false; l.fn = pick_preg<BF16T, 12, 4, 1, true>(preg, batched); return l; }
+        l.fn = pick_preg<BF16T, 12, 4, 1>(preg, batched); return l;
       case 16:                                                      // d = 128
         switch (variant) {
           case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg, batched); return l;
+          case 4: l.query_in_regs = false; l.fn = pick_preg<BF16T, 16, 4, 1, true>(preg, batched); return l;
           default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;
         }
       default: break;
@@ -727,18 +772,27 @@ struct Table<BF16T> {
     return l;
   }
 };
-template <>
-struct Table<FP8T> {
-  static Launch pick(int dc, int preg, int, bool batched) {
+template <typename F>
+struct Fp8Table {
+  static Launch pick(int dc, int preg, bool batched) {
     Launch l{nullptr, preg, true};
     switch (dc) {
-      case 6: l.fn = pick_preg<FP8T, 6, 4, 1>(preg, batched); return l;  // d = 96
-      case 8: l.fn = pick_preg<FP8T, 8, 4, 1>(preg, batched); return l;  // d = 128
+      case 6: l.fn = pick_preg<F, 6, 4, 1>(preg, batched); return l;  // d = 96
+      case 8: l.fn = pick_preg<F, 8, 4, 1>(preg, batched); return l;  // d = 128
       default: break;
     }
     l.query_in_regs = false;
-    l.fn = pick_preg<FP8T, 0, 16, 2>(preg, batched);
+    l.fn = pick_preg<F, 0, 16, 2>(preg, batched);
     return l;
+  }
+};
+// FP8: the conversion instruction by default (checked code by code against the
+// format definition); variant 1 keeps the bit-placement decode
+template <>
+struct Table<FP8T> {
+  static Launch pick(int dc, int preg, int variant, bool batched) {
+    return variant == 1 ? Fp8Table<FP8T>::pick(dc, preg, batched)
+                        : Fp8Table<FP8HwT>::pick(dc, preg, batched);
   }
 };
 
@@ -794,7 +848,10 @@ int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, bool exact
     if (rerank) table = std::max(table, (size_t)lcap * 8);
     *hash_log2_out = 0;
   } else {
-    int hl = hash_log2_req > 0 ? hash_log2_req : 11;
+    // default table: 2048 ids for FP32 vectors, 1024 for BF16 / FP8, whose
+    // cheaper recomputation favours the smaller LDS footprint (measured on the
+    // 1M x 128 workload)
+    int hl = hash_log2_req > 0 ? hash_log2_req : (dtype == SSG_F32 ? 11 : 10);
     // the table must hold the pool plus one row at load <= 1/2
     while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
     if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");

@@ -10,8 +10,9 @@ every workload here is drawn from a seeded mixture with the same shape:
            rank-16 Gaussian clusters, clipped and rounded (LID about 13).
 * ``c3``   1,000,000 x 960 values in [0, 1] (GIST-like), 500 overlapping
            rank-20 clusters around a Dirichlet-shaped mean profile (LID about 28).
-* ``c4``   1,000,000 x 96 unit-norm low-rank mixture (Deep-like), inner
-           product, queries with per-query pool size L and result count K.
+* ``c4``   1,000,000 x 96 unit-norm points of one shared rank-12 latent space
+           with overlapping clusters (Deep-like), inner product, queries with
+           per-query pool size L and result count K.
 * ``c5``   5,000,000 x 96, the c4 distribution, for the serving loop.
 * ``*s``   small variants of the same distributions for parity tests.
 
@@ -51,15 +52,15 @@ CONFIGS: dict[str, dict] = {
     "c3s": dict(kind="dirichlet", n=8_000, d=960, comps=20, rank=20, eps=0.003,
                 nq_unindexed=100, nq_indexed=4, knn_k=60, l=120, R=50,
                 alpha=60.0, s=10, L=100, K=10, metric="l2", seed=3100),
-    "c4": dict(kind="unit_lowrank", n=1_000_000, d=96, comps=1000, rank=16,
+    "c4": dict(kind="unit_lowrank", n=1_000_000, d=96, comps=1000, rank=12,
                nq_unindexed=100_000, nq_indexed=0, knn_k=100, l=100, R=50,
                alpha=60.0, s=10, L=128, K=10, metric="ip", seed=4000,
                L_choices=list(range(16, 513, 16)), K_choices=[1, 10, 100]),
-    "c4s": dict(kind="unit_lowrank", n=20_000, d=96, comps=40, rank=16,
+    "c4s": dict(kind="unit_lowrank", n=20_000, d=96, comps=40, rank=12,
                 nq_unindexed=2_000, nq_indexed=0, knn_k=60, l=100, R=50,
                 alpha=60.0, s=10, L=128, K=10, metric="ip", seed=4100,
                 L_choices=list(range(16, 513, 16)), K_choices=[1, 10, 100]),
-    "c5": dict(kind="unit_lowrank", n=5_000_000, d=96, comps=5000, rank=16,
+    "c5": dict(kind="unit_lowrank", n=5_000_000, d=96, comps=5000, rank=12,
                nq_unindexed=95_000, nq_indexed=5_000, knn_k=64, l=100, R=32,
                alpha=60.0, s=10, L=96, K=10, metric="ip", seed=5000,
                L_choices=list(range(32, 257, 16)), K_choices=[10],
@@ -95,9 +96,13 @@ def _params(cfg: dict):
         V = rng.normal(0.0, cfg.get("u_std", 0.03), (k, d, cfg["rank"]))
         return rng, dict(mu=mu, U=V)
     if kind == "unit_lowrank":
-        mu = rng.standard_normal((k, d))
-        W = rng.normal(0.0, 0.35, (k, d, cfg["rank"]))
-        return rng, dict(mu=mu, U=W)
+        # one shared rank-r latent space (projection A) holding overlapping
+        # Gaussian clusters; points are A u + noise, normalised to unit length,
+        # so the data is one connected low-dimensional piece of the sphere
+        r = cfg["rank"]
+        A = rng.standard_normal((d, r))
+        mu = rng.normal(0.0, cfg.get("c_spread", 1.0), (k, r))
+        return rng, dict(A=A, mu=mu)
     raise ValueError(kind)
 
 
@@ -112,6 +117,17 @@ def _draw(cfg: dict, p: dict, rng: np.random.Generator, m: int) -> np.ndarray:
         c = hi - lo
         if kind == "gmm_iso":
             x = p["mu"][lab] + cfg["sigma"] * rng.standard_normal((c, d))
+        elif kind == "unit_lowrank":
+            r = cfg["rank"]
+            u = p["mu"][lab] + cfg.get("u_spread", 0.8) * rng.standard_normal((c, r))
+            x = np.zeros((c, d))
+            for t in range(r):  # element-wise projection (no BLAS)
+                x += u[:, t:t + 1] * p["A"][:, t][None, :]
+            x += rng.normal(0.0, cfg.get("eps", 0.3), (c, d))
+            s = np.zeros(c)
+            for j in range(d):  # fixed-order squared norm
+                s += x[:, j] * x[:, j]
+            x = x / np.sqrt(s)[:, None]
         else:
             r = cfg["rank"]
             z = rng.standard_normal((c, r))
@@ -121,15 +137,9 @@ def _draw(cfg: dict, p: dict, rng: np.random.Generator, m: int) -> np.ndarray:
             if kind == "gmm_int":
                 x += rng.normal(0.0, 1.0, (c, d))
                 x = np.rint(np.clip(x, 0.0, 255.0))
-            elif kind == "dirichlet":
+            else:  # dirichlet
                 x += rng.normal(0.0, cfg.get("eps", 0.01), (c, d))
                 x = np.clip(x, 0.0, 1.0)
-            else:  # unit_lowrank
-                x += rng.normal(0.0, 0.05, (c, d))
-                s = np.zeros(c)
-                for j in range(d):  # fixed-order squared norm
-                    s += x[:, j] * x[:, j]
-                x = x / np.sqrt(s)[:, None]
         out[lo:hi] = x.astype(np.float32)
     return out
 

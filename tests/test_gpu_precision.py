@@ -127,3 +127,32 @@ def test_precision_search_parity(wl, fmt):
         fin = np.isfinite(rd[rows])
         err = np.abs(hd[rows][fin] - rd[rows][fin]) / np.maximum(np.abs(rd[rows][fin]), 1e-6)
         assert err.max() < 1e-4  # reranked distances are FP32 re-scores of FP64 keys
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp8_decode_of_every_code(variant):
+    """Each finite E4M3 code goes through the search kernel's decode: row c
+    holds code c in dimension 0 (scale 1), the graph is complete and the pool
+    holds every row, so the returned squared distance to the query (1, 0, ...)
+    is (1 - value(c))^2 for every code."""
+    from paper_1907_06146_amd import search
+    codes = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], np.uint8)
+    n, d = len(codes), 16
+    base = np.zeros((n, d), np.uint8)
+    base[:, 0] = codes
+    scale = np.ones(d, np.float32)
+    g = np.array([[j for j in range(n) if j != i][:64] for i in range(n)], np.uint32)
+    g[:, :] = SENT
+    for i in range(n):  # a ring with chords: every node reachable, 64 edges per row
+        g[i] = (i + 1 + np.arange(64) * 4) % n
+    q = np.zeros((1, d), np.float32)
+    q[0, 0] = 1.0
+    ids, dd = search(_dev(base), _dev(g), _dev(np.array([0], np.uint32)), _dev(q), n, 512,
+                     dim_scale=_dev(scale), gather_variant=variant)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()[0]
+    dd = dd.cpu().numpy()[0]
+    assert sorted(ids.tolist()) == list(range(n))
+    val = P.fp8_decode(codes).astype(np.float64)
+    want = ((1.0 - val) ** 2).astype(np.float32)
+    assert np.array_equal(dd, want[ids])
