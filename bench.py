@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2: the headline search; c4: mixed L/K batched form; c5: serving")
+    ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
+    ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: 3 launches of the timed configuration, then a 1 GiB "
                          "element-wise copy whose bytes calibrate the counters; no output")
@@ -95,6 +99,12 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload == "c4":
+        print(json.dumps(bench_batched(a)), flush=True)
+        return
+    if a.workload == "c5":
+        print(json.dumps(bench_serving(a)), flush=True)
+        return
     cfg = synth.CONFIGS[WORKLOAD]
     t0 = time.time()
     gc = graph_io.load(WORKLOAD)
@@ -166,6 +176,8 @@ def main():
     bytes_launch = float(bq.sum())
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
     traffic = traffic_from_profile("c2_search_f32")
+    ceiling = gather_ceiling(tb, base.shape[1] * 4, int(np.sum(ondc)))
+    log(f"random {base.shape[1] * 4}-byte row gather ceiling: {ceiling:.0f} GB/s")
     out = {
         "metric": "queries/sec at recall@10>=0.95 (1Mx128, 1 GPU); achieved HBM GB/s vs peak",
         "value": qps,
@@ -189,7 +201,8 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_query": float(bq.mean()),
                      "oracle_ndc_mean": float(np.mean(ondc)), "oracle_hops_mean": float(np.mean(ohops)),
-                     "gpu_ndc_mean": float(gndc.mean())},
+                     "gpu_ndc_mean": float(gndc.mean()),
+                     "gather_ceiling_GBps": ceiling, "frac_of_gather_ceiling": achieved / ceiling},
         "kernel_source": source_digest(),
     }
     if not a.no_forms:
@@ -212,6 +225,30 @@ def _time(fn, steps, warmup, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def gather_ceiling(base_t, row_bytes, m, seed=0, rows_per_wave=16):
+    """Random-row gather rate of the device in the search's access shape
+    (ssg_probe_gather): m uniformly random rows of row_bytes, GB/s."""
+    import ctypes
+
+    import torch
+
+    from paper_1907_06146_amd import _lib
+    dev = base_t.device
+    n = base_t.shape[0]
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    ids = torch.randint(0, n, (m,), dtype=torch.int32, device=dev, generator=g)
+    out = torch.empty((m + rows_per_wave - 1) // rows_per_wave, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+
+    def fn():
+        _lib.check(_lib.lib().ssg_probe_gather(
+            ctypes.c_void_p(base_t.data_ptr()), n, row_bytes, ctypes.c_void_p(ids.data_ptr()), m,
+            rows_per_wave, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+    ms = _time(fn, 5, 2, st)
+    return m * row_bytes / (ms / 1e3) / 1e9
 
 
 def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
@@ -244,10 +281,11 @@ def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
                 eb = 2 if fmt == "bf16" else 1
                 bq = 4 * d + cfg["s"] * d * eb + hops * 4 * tg.shape[1] + (ndc - cfg["s"]) * d * eb \
                     + min(L, K) * d * 4 + 8 * K
+                ceil = gather_ceiling(codes, d * eb, int(nq * ndc))
                 best = {"L": L, "recall10": r10, "ms_per_step": ms, "qps": nq / ms * 1e3,
                         "speedup_vs_fp32": fp32_ms / ms, "gpu_ndc_mean": ndc,
                         "bytes_per_query": bq, "achieved_GBps": bq * nq / (ms / 1e3) / 1e9,
-                        "rerank": "fp32, whole pool"}
+                        "gather_ceiling_GBps": ceil, "rerank": "fp32, whole pool"}
                 break
         forms[fmt] = best
         log(f"form {fmt}: {best}")
@@ -256,6 +294,142 @@ def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
 
 def sweep_Ls(sweep):
     return [r["L"] for r in sweep["rows"]]
+
+
+def recall_mixed(ids, gt, K_arr):
+    """Mean over queries of |R n G| / K_i with each query's own K_i (Eq. 1)."""
+    hit = 0.0
+    for r, k in enumerate(K_arr):
+        x = ids[r, :k]
+        hit += len(np.intersect1d(x[x >= 0], gt[r, :k])) / float(k)
+    return hit / len(K_arr)
+
+
+def _load(name):
+    import synth
+    from paper_1907_06146_amd import graph_io
+    cfg = synth.CONFIGS[name]
+    gc = graph_io.load(name)
+    base = synth.base_vectors(cfg)
+    if synth.checksum(base) != gc["meta"]["base_sha"]:
+        raise SystemExit(f"regenerated {name} base vectors do not match the graph cache")
+    q = synth.queries(cfg, base)
+    droot = os.path.join(graph_io.default_root(), name)
+    gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
+    return cfg, gc, base, q, gt
+
+
+def bench_batched(a):
+    """Deep-shaped 1M x 96 unit-norm workload, inner product, 100,000 queries
+    with their own L in {16..512} and K in {1, 10, 100}: the plain FP32 search
+    launched once per (L, K) group, against one graph-captured persistent
+    batched launch (FP32, and BF16 with an FP32 rerank of each query's K)."""
+    import torch
+
+    import synth
+    from paper_1907_06146_amd import graph_io, quantize, search
+    from paper_1907_06146_amd.autotune import tune
+    from paper_1907_06146_amd.batched import BatchedSearch
+
+    t0 = time.time()
+    cfg, gc, base, q, gt = _load("c4")
+    Lq, Kq = synth.query_params("c4")
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    tq = torch.from_numpy(q).to(dev)
+    nq = len(q)
+    kst = int(Kq.max())
+    stream = torch.cuda.current_stream()
+    log(f"c4 ready in {time.time() - t0:.1f}s: n={len(base)} nq={nq}")
+    # plain: one launch per (L, K) group
+    groups = {}
+    for i, key in enumerate(zip(Lq.tolist(), Kq.tolist())):
+        groups.setdefault(key, []).append(i)
+    plan = []
+    for (L, K), rows in sorted(groups.items()):
+        rows = np.asarray(rows)
+        tr = torch.from_numpy(rows).to(dev)
+        plan.append((L, K, rows, tq[tr].contiguous(),
+                     torch.empty((len(rows), K), dtype=torch.int32, device=dev),
+                     torch.empty((len(rows), K), dtype=torch.float32, device=dev)))
+
+    def plain():
+        for L, K, rows, qq, oi, od in plan:
+            search(tb, tg, te, qq, K, L, "ip", out=(oi, od))
+    ms_plain = _time(plain, max(3, a.steps // 4), 1, stream)
+    ids_plain = np.full((nq, kst), -1, np.int32)
+    for L, K, rows, qq, oi, od in plan:
+        ids_plain[rows, :K] = oi.cpu().numpy()
+    r_plain = recall_mixed(ids_plain, gt, Kq)
+    log(f"plain fp32: {len(plan)} launches, {ms_plain:.3f} ms, recall {r_plain:.4f}")
+    out = {"metric": "mixed-L/K batch queries/s at equal recall (1M x 96 unit-norm, IP, 1 GPU)",
+           "unit": "queries/s", "workload": "deep-shaped synthetic 1,000,000 x 96, 100,000 "
+           "queries, L in {16..512}, K in {1, 10, 100}", "n_gpus": 1,
+           "plain_fp32": {"launches": len(plan), "ms": ms_plain, "qps": nq / ms_plain * 1e3,
+                          "recall_at_Ki": r_plain}}
+    qb, _ = quantize(tb, "bf16")
+    tune_path = os.path.join(graph_io.default_root(), "autotune.json")
+    for name, bse, kw in (("batched_fp32", tb, {}),
+                          ("batched_bf16_rerank", qb, dict(base_f32=tb, rerank=-1))):
+        t = time.time()
+        shapes = tune(bse, tg, te, tq, Lq, Kq, "ip", sample=2048, reps=2, cache_path=tune_path, **kw)
+        log(f"{name}: tuned in {time.time() - t:.1f}s: {shapes}")
+        bs = BatchedSearch(bse, tg, te, tq, Lq, Kq, "ip", shapes=shapes, use_graph=True, **kw)
+        ms = _time(bs.run, max(3, a.steps // 4), 1, stream)
+        ids = bs.out_ids.cpu().numpy()
+        r = recall_mixed(ids, gt, Kq)
+        same = float(np.mean((ids == ids_plain).all(1)))
+        out[name] = {"ms": ms, "qps": nq / ms * 1e3, "recall_at_Ki": r, "speedup_vs_plain": ms_plain / ms,
+                     "rows_equal_to_plain": same, "shapes": {str(k): v for k, v in shapes.items()}}
+        log(f"{name}: {ms:.3f} ms, recall {r:.4f}, x{ms_plain / ms:.2f}")
+        bs.close()
+    out["value"] = out["batched_bf16_rerank"]["qps"]
+    return out
+
+
+def bench_serving(a):
+    """Serving: 5M x 96 unit-norm base (BF16 search, FP32 rerank of K = 10)
+    resident in HBM; Poisson arrivals of requests of 1..256 queries with one
+    L in {32..256}; continuous batching over 8 slots."""
+    import torch
+
+    from paper_1907_06146_amd import graph_io, quantize
+    from paper_1907_06146_amd.serve import GpuDevice, Scheduler, poisson_requests, run, summarize
+
+    t0 = time.time()
+    cfg, gc, base, q, gt = _load("c5")
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    qb, _ = quantize(tb, "bf16")
+    torch.cuda.synchronize()
+    log(f"c5 ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(cfg["seed"] + 5)
+    reqs, picks = poisson_requests(rng, a.requests, a.offered_rps, q, cfg["L_choices"], cfg["K"],
+                                   max_batch=256)
+    n_slots = 8
+    gdev = GpuDevice(qb, tg, te, n_slots=n_slots, max_batch=256, max_K=cfg["K"], metric="ip",
+                     base_f32=tb, rerank=True)
+    warm, _ = poisson_requests(np.random.default_rng(1), 50, 1e6, q, [64], cfg["K"], max_batch=64)
+    run(warm, Scheduler(gdev, n_slots, 4096))
+    sch = Scheduler(gdev, n_slots=n_slots, inflight_budget=6144)
+    done = run(reqs, sch)
+    s = summarize(done)
+    hit = 0.0
+    nqs = 0
+    for r, p in zip(sorted(done, key=lambda r: r.rid), picks):
+        for row, qi in zip(r.ids, p):
+            hit += len(np.intersect1d(row[row >= 0], gt[qi, :10])) / 10.0
+            nqs += 1
+    s.update(recall10=hit / nqs, offered_rps=a.offered_rps,
+             offered_qps=a.offered_rps * np.mean([len(r.queries) for r in reqs]),
+             slots=n_slots, max_running=sch.max_running_seen)
+    log(f"serving: {s}")
+    return {"metric": "serving queries/s and p50/p99 latency (5M x 96, BF16 + FP32 rerank, 1 GPU)",
+            "value": s["qps"], "unit": "queries/s", "n_gpus": 1, **s}
 
 
 def cpu_baseline(base, gc, q, K, L, cfg, sample):

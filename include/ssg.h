@@ -195,6 +195,18 @@ int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
 int ssg_batch_graph_launch(ssg_batch_graph* g, void* stream);
 int ssg_batch_graph_destroy(ssg_batch_graph* g);
 
+/*
+ * ssg_probe_gather -- measurement aid (not part of the method): reads the rows
+ * base[ids[i]] (row_bytes each) in the search kernel's access shape and
+ * writes one checksum word per wavefront, so the random-row gather rate of the
+ * device can be measured on its own.
+ *   base  DEVICE, n rows of row_bytes (a positive multiple of 16), 16-byte aligned
+ *   ids   DEVICE uint32[m], each < n (not checked on the device)
+ *   out   DEVICE uint32[ceil(m / rows_per_wave)]
+ */
+int ssg_probe_gather(const void* base, int64_t n, int32_t row_bytes, const uint32_t* ids,
+                     int64_t m, int32_t rows_per_wave, uint32_t* out, void* stream);
+
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
 

@@ -17,3 +17,4 @@ def quantize(*args, **kwargs):
     """See ``binding.quantize``."""
     from .binding import quantize as _quantize
     return _quantize(*args, **kwargs)
+

@@ -23,7 +23,7 @@ L_MAX, R_MAX, K_MAX = 512, 64, 4096
 EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_bytes",
            "ssg_validate_graph", "ssg_last_error", "ssg_version", "ssg_batch_workspace_bytes",
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
-           "ssg_batch_graph_destroy")
+           "ssg_batch_graph_destroy", "ssg_probe_gather")
 
 
 class SSGError(RuntimeError):
@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
             L.ssg_batch_graph_launch.restype = ctypes.c_int
             L.ssg_batch_graph_destroy.argtypes = [P]
             L.ssg_batch_graph_destroy.restype = ctypes.c_int
+            L.ssg_probe_gather.argtypes = [P, i64, i32, P, i64, i32, P, P]
+            L.ssg_probe_gather.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

@@ -83,6 +83,27 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
   uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
   return ((uint64_t)hi << 32) | lo;
 }
+// Minimum of a 64-bit value over the wavefront, read back on every lane.
+// Row-local DPP shifts (VALU latency, not the LDS pipe of lane shuffles)
+// reduce each row of 16 into its lane 15; row broadcasts fold the four rows
+// into lane 63.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_min64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0xFFFFFFFFu, (uint32_t)v, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0xFFFFFFFFu, (uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  const uint64_t o = ((uint64_t)hi << 32) | lo;
+  return o < v ? o : v;
+}
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
+  v = dpp_min64<0x111>(v);  // row_shr:1
+  v = dpp_min64<0x112>(v);  // row_shr:2
+  v = dpp_min64<0x114>(v);  // row_shr:4
+  v = dpp_min64<0x118>(v);  // row_shr:8
+  v = dpp_min64<0x142>(v);  // row_bcast:15
+  v = dpp_min64<0x143>(v);  // row_bcast:31
+  return readlane64(v, 63);
+}
+
 __device__ __forceinline__ int lane_prefix(uint64_t mask) {  // set bits below this lane
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -350,15 +371,13 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       const uint32_t old = atomicOr(&table[id >> 5], bit);
       return (old & bit) == 0u;
     }
+    // one LDS compare-and-swap per probe: an empty slot takes the id, a slot
+    // holding the id means visited, anything else moves to the next slot
     uint32_t h = hash_slot(id, hmask);
     for (;;) {
-      const uint32_t cur = table[h];
-      if (cur == id) return false;
-      if (cur == kSent) {
-        const uint32_t old = atomicCAS(&table[h], kSent, id);
-        if (old == kSent) return true;
-        if (old == id) return false;
-      }
+      const uint32_t old = atomicCAS(&table[h], kSent, id);
+      if (old == kSent) return true;
+      if (old == id) return false;
       h = (h + 1u) & hmask;
     }
   };
@@ -381,8 +400,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       if (lane < m) best = min(best, bkeys[lane]);
       wave_sync();
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) best = min(best, shfl_xor64(best, off));
+    best = wave_min64(best);
     ndc = a.s;
     if (lane == 0) pool[0] = best | 1ull;
     size = 1;
@@ -407,6 +425,18 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       wave_sync();
       hcount = size;
     }
+
+    // speculation: the first unchecked pool entry is the next expansion unless
+    // a new key beats it; read its row now, alongside this hop's gathers
+    uint64_t u = kNoKey;
+#pragma unroll
+    for (int k = 0; k < PREG; ++k) {
+      const uint64_t um = __ballot((pool[k] & 1ull) == 0ull);
+      if (u == kNoKey && um) u = readlane64(pool[k], __builtin_ctzll(um));
+    }
+    const uint64_t u_spec = u;
+    const uint32_t nb_spec =
+        u_spec != kNoKey && lane < R ? a.graph[(size_t)key_id(u_spec) * R + lane] : kSent;
 
     // visited filter and compaction of the row's new ids
     const bool fresh = nb != kSent && visit(nb);
@@ -436,25 +466,13 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     // next expansion, decided before the merge so its row read overlaps it:
     // the smallest unchecked key u of (pool + new keys) is kept iff fewer
     // than L keys precede it; otherwise every kept entry is checked.
-    uint64_t u = kNoKey;
-#pragma unroll
-    for (int k = 0; k < PREG; ++k) {
-      const uint64_t um = __ballot((pool[k] & 1ull) == 0ull);
-      if (u == kNoKey && um) u = readlane64(pool[k], __builtin_ctzll(um));
-    }
-    uint64_t bmin = b;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) bmin = min(bmin, shfl_xor64(bmin, off));
-    u = min(u, bmin);
+    u = min(u, wave_min64(b));
     int rank_u = __popcll(__ballot(b < u));
 #pragma unroll
     for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
     const bool more = u != kNoKey && rank_u < L;
-    uint32_t nb_next = kSent;
-    if (more) {
-      p = key_id(u);
-      nb_next = lane < R ? a.graph[(size_t)p * R + lane] : kSent;
-    }
+    uint32_t nb_next = nb_spec;
+    if (more && u != u_spec) nb_next = lane < R ? a.graph[(size_t)key_id(u) * R + lane] : kSent;
 
     // rank-based merge of the surviving new keys into the pool, truncated to L
     if (bm) {
@@ -675,6 +693,34 @@ __global__ void encode_kernel(const float* x, int64_t n, int d, int dtype, const
       static_cast<uint8_t*>(out)[i] = (uint8_t)fp8_e4m3_rne(__fdiv_rn(v, scale[j]));
     }
   }
+}
+
+// ------------------------------------------------------------------ gather probe
+// Measurement aid: the search's memory access shape without the search. Each
+// wavefront reads rows ids[i] (row_bytes each, 16-byte chunks spread over G
+// lanes per row, 64/G rows per pass) and folds every word into a checksum so
+// no load can be dropped; one word per wavefront is written.
+template <int G>
+__global__ __launch_bounds__(256) void gather_probe_kernel(const uint4* base, int chunks,
+                                                           const uint32_t* ids, int64_t m,
+                                                           int64_t per_wave, uint32_t* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t lo = w * per_wave;
+  const int64_t hi = min(m, lo + per_wave);
+  uint32_t acc = 0u;
+  for (int64_t r0 = lo; r0 < hi; r0 += 64 / G) {
+    const int64_t r = r0 + lane / G;
+    if (r < hi) {
+      const uint4* row = base + (size_t)ids[r] * chunks;
+      for (int c = lane % G; c < chunks; c += G) {
+        const uint4 v = row[c];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+      }
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+  if (lane == 0 && lo < m) out[w] = acc;
 }
 
 // ------------------------------------------------------------------ host side
@@ -960,6 +1006,31 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   const int64_t blocks = (nq + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return fail(SSG_EINVAL, "too many queries");
   hipLaunchKernelGGL(lc.fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
+  g_err.clear();
+  return SSG_OK;
+}
+
+int ssg_probe_gather(const void* base, int64_t n, int32_t row_bytes, const uint32_t* ids,
+                     int64_t m, int32_t rows_per_wave, uint32_t* out, void* stream) {
+  if (!base || !ids || !out || n < 1 || m < 0 || rows_per_wave < 1)
+    return fail(SSG_EINVAL, "bad probe arguments");
+  if (row_bytes < 16 || row_bytes % 16 || reinterpret_cast<uintptr_t>(base) % 16)
+    return fail(SSG_EINVAL, "row_bytes must be a positive multiple of 16, base 16-byte aligned");
+  if (m == 0) { g_err.clear(); return SSG_OK; }
+  const int chunks = row_bytes / 16;
+  const int64_t waves = (m + rows_per_wave - 1) / rows_per_wave;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks > 0x7FFFFFFF) return fail(SSG_EINVAL, "too many rows");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint4* b = static_cast<const uint4*>(base);
+  if (chunks >= 32)
+    hipLaunchKernelGGL(gather_probe_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, b, chunks,
+                       ids, m, (int64_t)rows_per_wave, out);
+  else
+    hipLaunchKernelGGL(gather_probe_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, b, chunks,
+                       ids, m, (int64_t)rows_per_wave, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
   g_err.clear();
