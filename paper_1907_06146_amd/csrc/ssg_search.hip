@@ -301,6 +301,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
 #pragma unroll
       for (int p = 0; p < NP; ++p) acc[p] = 0.f;
       if constexpr (kCompiled) {
+        // with the query in LDS, re-read it per pass instead of letting the
+        // compiler keep a register copy (the point is to free those registers)
+        if constexpr (!kQueryInRegs) __asm__ volatile("" ::: "memory");
         uint4 buf[NP][NCH];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {

@@ -137,3 +137,43 @@ def test_autotuner_picks_valid_shapes(c4s, tmp_path):
     assert same.mean() >= 0.99  # shapes change only the reduction order of float sums
     bs.close()
     ref.close()
+
+
+def test_c4_full_size_batched_against_stored_oracle():
+    """Full Deep-shaped workload (1M x 96, 100,000 queries with their own L
+    and K) in one graph-captured persistent launch, against the oracle's
+    stored per-query results; float data, so differing rows must be explained
+    by FP64 key ties."""
+    from oracle import cache
+    from paper_1907_06146_amd.batched import BatchedSearch
+    meta = cache.load_meta("c4")
+    if meta is None or not cache.exists("c4", "oracle_mixed_ids"):
+        pytest.skip("1M x 96 cache not built")
+    cfg = synth.CONFIGS["c4"]
+    base = synth.base_vectors(cfg)
+    assert synth.checksum(base) == meta["base_sha"]
+    q = synth.queries(cfg, base)
+    Lq, Kq = synth.query_params(cfg)
+    g = cache.load("c4", "graph")
+    entry = cache.load("c4", "entry_ids")
+    bs = BatchedSearch(_dev(base), _dev(g), _dev(entry), _dev(q), Lq, Kq, "ip", stats=True)
+    ids, _ = bs.run()
+    torch.cuda.synchronize()
+    gi = ids.cpu().numpy().view(np.uint32)
+    oi = cache.load("c4", "oracle_mixed_ids")
+    from parity_util import classify
+    exact, explained, genuine = classify(base, q, gi, oi, "ip")
+    print(f"c4 full size: exact {exact.mean():.5f} explained {explained.mean():.5f} "
+          f"genuine {genuine.mean():.5f}")
+    assert (exact | explained).mean() >= 0.999
+    oh = cache.load("c4", "oracle_mixed_hops")
+    # float data: a near-tie deep in the pool can reorder expansions without
+    # changing the returned K_i, so hop counts agree on most, not all, rows
+    assert (bs.hops.cpu().numpy()[exact] == oh[exact]).mean() >= 0.99
+    gt = cache.load("c4", "gt_ids") if cache.exists("c4", "gt_ids") else None
+    if gt is not None:  # recall at each query's own K within 0.001 of the oracle's
+        def rec(ids):
+            return np.mean([len(set(ids[r, :k].tolist()) & set(gt[r, :k].tolist())) / k
+                            for r, k in enumerate(Kq)])
+        assert abs(rec(gi) - rec(oi)) <= 0.001
+    bs.close()
