@@ -85,6 +85,7 @@ def main():
                     help="c2: the headline search; c4: mixed L/K batched form; c5: serving")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
+    ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: 3 launches of the timed configuration, then a 1 GiB "
                          "element-wise copy whose bytes calibrate the counters; no output")
@@ -401,6 +402,11 @@ def bench_batched(a):
     return out
 
 
+def synth_cfg(name):
+    import synth
+    return synth.CONFIGS[name]
+
+
 def bench_serving(a):
     """Serving: 5M x 96 unit-norm base (BF16 search, FP32 rerank of K = 10)
     resident in HBM; Poisson arrivals of requests of 1..256 queries with one
@@ -411,21 +417,22 @@ def bench_serving(a):
     from paper_1907_06146_amd.serve import GpuDevice, Scheduler, poisson_requests, run, summarize
 
     t0 = time.time()
-    cfg, gc, base, q, gt = _load("c5")
+    cfg, gc, base, q, gt = _load(a.serve_data)
+    scfg = synth_cfg("c5")
     dev = torch.device("cuda:0")
     tb = torch.from_numpy(base).to(dev)
     tg = graph_io.to_device(gc["graph"], dev)
     te = graph_io.to_device(gc["entry_ids"], dev)
     qb, _ = quantize(tb, "bf16")
     torch.cuda.synchronize()
-    log(f"c5 ready in {time.time() - t0:.1f}s")
-    rng = np.random.default_rng(cfg["seed"] + 5)
-    reqs, picks = poisson_requests(rng, a.requests, a.offered_rps, q, cfg["L_choices"], cfg["K"],
+    log(f"{a.serve_data} ready in {time.time() - t0:.1f}s: n={len(base)}")
+    rng = np.random.default_rng(scfg["seed"] + 5)
+    reqs, picks = poisson_requests(rng, a.requests, a.offered_rps, q, scfg["L_choices"], scfg["K"],
                                    max_batch=256)
     n_slots = 8
-    gdev = GpuDevice(qb, tg, te, n_slots=n_slots, max_batch=256, max_K=cfg["K"], metric="ip",
+    gdev = GpuDevice(qb, tg, te, n_slots=n_slots, max_batch=256, max_K=scfg["K"], metric="ip",
                      base_f32=tb, rerank=True)
-    warm, _ = poisson_requests(np.random.default_rng(1), 50, 1e6, q, [64], cfg["K"], max_batch=64)
+    warm, _ = poisson_requests(np.random.default_rng(1), 50, 1e6, q, [64], scfg["K"], max_batch=64)
     run(warm, Scheduler(gdev, n_slots, 4096))
     sch = Scheduler(gdev, n_slots=n_slots, inflight_budget=6144)
     done = run(reqs, sch)
@@ -440,8 +447,9 @@ def bench_serving(a):
              offered_qps=a.offered_rps * np.mean([len(r.queries) for r in reqs]),
              slots=n_slots, max_running=sch.max_running_seen)
     log(f"serving: {s}")
-    return {"metric": "serving queries/s and p50/p99 latency (5M x 96, BF16 + FP32 rerank, 1 GPU)",
-            "value": s["qps"], "unit": "queries/s", "n_gpus": 1, **s}
+    return {"metric": "serving queries/s and p50/p99 latency (BF16 + FP32 rerank, 1 GPU)",
+            "index": f"{a.serve_data}: {len(base)} x {base.shape[1]}", "value": s["qps"],
+            "unit": "queries/s", "n_gpus": 1, **s}
 
 
 def cpu_baseline(base, gc, q, K, L, cfg, sample):
