@@ -207,6 +207,37 @@ int ssg_batch_graph_destroy(ssg_batch_graph* g);
 int ssg_probe_gather(const void* base, int64_t n, int32_t row_bytes, const uint32_t* ids,
                      int64_t m, int32_t rows_per_wave, uint32_t* out, void* stream);
 
+/*
+ * ssg_knn_graph -- exact K-nearest-neighbour graph by brute force: the kNN
+ * graph the indexing algorithm starts from (Alg. 3; the paper builds it
+ * approximately, this builds it exactly), on the device's matrix cores.
+ *   base        DEVICE float32 n x d row-major (16-byte aligned rows give
+ *               vector loads), finite values
+ *   n, d        2 <= n <= 2^25, d >= 1
+ *   K           1 <= K <= min(100, n - 1)
+ *   out_ids     DEVICE uint32 n x K: row i lists the K points nearest to
+ *               point i, itself excluded, in ascending (squared Euclidean
+ *               distance, id) order; the distance is the FP64 sum of
+ *               (x_ij - x_kj)^2 over the dimensions in order
+ *   out_dists   DEVICE float32 n x K: those distances rounded to float32
+ *   workspace   DEVICE, 256-byte aligned, ssg_knn_workspace_bytes(n, d, K)
+ *               bytes, owned by the caller, contents on entry ignored
+ *   stats       HOST int64[4] or NULL: [0] 1 if the exact integer path ran
+ *               (all values integers in [0, 255] and d <= 128), [1] rows
+ *               whose certificate failed and were rescanned in FP64,
+ *               [2] candidates kept per row, [3] reserved
+ *   stream      hipStream_t (NULL: the legacy default stream)
+ * Synchronous: the call waits on its stream (it reads two flag words back).
+ * Returns SSG_OK; SSG_EINVAL for bad arguments; SSG_EDEVICE on a launch or
+ * device error; SSG_EUNSUPPORTED if more than 4096 points tie at or below
+ * some row's K-th distance, or if more than 1024 rows fail the certificate
+ * and their FP64 rescans would evaluate more than 2^36 pairs.
+ */
+size_t ssg_knn_workspace_bytes(int64_t n, int32_t d, int32_t K);
+int ssg_knn_graph(const float* base, int64_t n, int32_t d, int32_t K, uint32_t* out_ids,
+                  float* out_dists, void* workspace, size_t workspace_bytes, int64_t* stats,
+                  void* stream);
+
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
 

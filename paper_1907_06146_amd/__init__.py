@@ -18,3 +18,8 @@ def quantize(*args, **kwargs):
     from .binding import quantize as _quantize
     return _quantize(*args, **kwargs)
 
+
+def knn_graph(*args, **kwargs):
+    """See ``binding.knn_graph``."""
+    from .binding import knn_graph as _knn
+    return _knn(*args, **kwargs)

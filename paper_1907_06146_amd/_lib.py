@@ -1,6 +1,7 @@
 """ctypes binding of libssg (include/ssg.h). Argument marshalling only.
 
-Every step of the search runs in the HIP kernels of ``csrc/ssg_search.hip``.
+Every step runs in the HIP kernels of ``csrc/ssg_search.hip`` (search) and
+``csrc/ssg_knn.hip`` (kNN graph).
 There is no CPU or PyTorch fallback: if the shared library is missing or
 cannot be loaded, every call raises.
 """
@@ -23,7 +24,8 @@ L_MAX, R_MAX, K_MAX = 512, 64, 4096
 EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_bytes",
            "ssg_validate_graph", "ssg_last_error", "ssg_version", "ssg_batch_workspace_bytes",
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
-           "ssg_batch_graph_destroy", "ssg_probe_gather")
+           "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
+           "ssg_knn_graph")
 
 
 class SSGError(RuntimeError):
@@ -96,6 +98,10 @@ def lib() -> ctypes.CDLL:
             L.ssg_batch_graph_destroy.restype = ctypes.c_int
             L.ssg_probe_gather.argtypes = [P, i64, i32, P, i64, i32, P, P]
             L.ssg_probe_gather.restype = ctypes.c_int
+            L.ssg_knn_workspace_bytes.argtypes = [i64, i32, i32]
+            L.ssg_knn_workspace_bytes.restype = sz
+            L.ssg_knn_graph.argtypes = [P, i64, i32, i32, P, P, P, sz, P, P]
+            L.ssg_knn_graph.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

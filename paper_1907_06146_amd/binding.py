@@ -111,3 +111,29 @@ def quantize(base_f32, dtype: str, stream=None):
         _lib.check(rc)
         return out, scale
     raise ValueError(f"unknown storage dtype {dtype}")
+
+
+def knn_graph(base, K: int, stream=None):
+    """Exact K-nearest-neighbour graph of the rows of ``base`` (float32
+    [n, d] on the GPU) by brute force on the matrix cores: row i lists the K
+    nearest other points in ascending (squared L2, id) order. Returns
+    (ids int32 [n, K], dists float32 [n, K], stats dict). Synchronous."""
+    _need_cuda("base", base, (torch.float32,))
+    n, d = base.shape
+    dev = base.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    L = _lib.lib()
+    nbytes = L.ssg_knn_workspace_bytes(n, d, K)
+    if nbytes == 0:
+        raise ValueError(f"invalid kNN shape n={n} d={d} K={K}")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    ids = torch.empty((n, K), dtype=torch.int32, device=dev)
+    dd = torch.empty((n, K), dtype=torch.float32, device=dev)
+    stats = (ctypes.c_int64 * 4)()
+    rc = L.ssg_knn_graph(_ptr(base), n, d, K, _ptr(ids), _ptr(dd), ctypes.c_void_p(ws.data_ptr() + off),
+                         nbytes, stats, ctypes.c_void_p(st.cuda_stream))
+    _lib.check(rc)
+    del ws
+    return ids, dd, {"exact_path": bool(stats[0]), "rescanned_rows": int(stats[1]),
+                     "candidates": int(stats[2])}

@@ -45,6 +45,7 @@
 #include <vector>
 
 #include "ssg.h"
+#include "ssg_internal.h"
 
 namespace {
 
@@ -913,6 +914,9 @@ int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, bool exact
 
 
 }  // namespace
+
+int ssg_internal_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+void ssg_internal_clear_error() { g_err.clear(); }
 
 extern "C" {
 

@@ -106,41 +106,75 @@ def _params(cfg: dict):
     raise ValueError(kind)
 
 
+def _chunk_values(cfg: dict, p: dict, lab: np.ndarray, z: np.ndarray, e: np.ndarray) -> np.ndarray:
+    """Rows of one chunk from its labels and its two blocks of draws (z, then
+    e). Element-wise IEEE operations only, so the result does not depend on
+    which thread computes it."""
+    kind = cfg["kind"]
+    c = len(lab)
+    if kind == "gmm_iso":
+        x = p["mu"][lab] + cfg["sigma"] * e
+    elif kind == "unit_lowrank":
+        u = p["mu"][lab] + cfg.get("u_spread", 0.8) * z
+        x = np.zeros((c, cfg["d"]))
+        for t in range(cfg["rank"]):  # element-wise projection (no BLAS)
+            x += u[:, t:t + 1] * p["At"][t][None, :]
+        x += e
+        s = np.zeros(c)
+        for j in range(cfg["d"]):  # fixed-order squared norm
+            s += x[:, j] * x[:, j]
+        x = x / np.sqrt(s)[:, None]
+    else:
+        x = p["mu"][lab]  # fancy indexing returns a copy
+        for t in range(cfg["rank"]):  # explicit element-wise low-rank product (no BLAS)
+            x += p["Ut"][t][lab] * z[:, t:t + 1]
+        x += e
+        if kind == "gmm_int":
+            x = np.rint(np.clip(x, 0.0, 255.0))
+        else:  # dirichlet
+            x = np.clip(x, 0.0, 1.0)
+    return x.astype(np.float32)
+
+
 def _draw(cfg: dict, p: dict, rng: np.random.Generator, m: int) -> np.ndarray:
-    """Draw m points of the mixture from ``rng``; returns float32 (m, d)."""
+    """Draw m points of the mixture from ``rng``; returns float32 (m, d).
+
+    The random stream is consumed in one fixed order (labels, then per chunk
+    of rows the latent draws and the noise); the arithmetic of each chunk runs
+    on a small thread pool (numpy releases the interpreter lock there)."""
+    import concurrent.futures as cf
+    import os
     d, k, kind = cfg["d"], cfg["comps"], cfg["kind"]
+    p = dict(p)
+    if "U" in p:
+        p["Ut"] = [np.ascontiguousarray(p["U"][:, :, t]) for t in range(cfg["rank"])]
+    if "A" in p:
+        p["At"] = [np.ascontiguousarray(p["A"][:, t]) for t in range(cfg["rank"])]
     out = np.empty((m, d), dtype=np.float32)
     labels = rng.integers(0, k, m)
-    for lo in range(0, m, _CHUNK):
-        hi = min(m, lo + _CHUNK)
-        lab = labels[lo:hi]
-        c = hi - lo
-        if kind == "gmm_iso":
-            x = p["mu"][lab] + cfg["sigma"] * rng.standard_normal((c, d))
-        elif kind == "unit_lowrank":
-            r = cfg["rank"]
-            u = p["mu"][lab] + cfg.get("u_spread", 0.8) * rng.standard_normal((c, r))
-            x = np.zeros((c, d))
-            for t in range(r):  # element-wise projection (no BLAS)
-                x += u[:, t:t + 1] * p["A"][:, t][None, :]
-            x += rng.normal(0.0, cfg.get("eps", 0.3), (c, d))
-            s = np.zeros(c)
-            for j in range(d):  # fixed-order squared norm
-                s += x[:, j] * x[:, j]
-            x = x / np.sqrt(s)[:, None]
-        else:
-            r = cfg["rank"]
-            z = rng.standard_normal((c, r))
-            x = p["mu"][lab].copy()
-            for t in range(r):  # explicit element-wise low-rank product (no BLAS)
-                x += p["U"][:, :, t][lab] * z[:, t:t + 1]
-            if kind == "gmm_int":
-                x += rng.normal(0.0, 1.0, (c, d))
-                x = np.rint(np.clip(x, 0.0, 255.0))
-            else:  # dirichlet
-                x += rng.normal(0.0, cfg.get("eps", 0.01), (c, d))
-                x = np.clip(x, 0.0, 1.0)
-        out[lo:hi] = x.astype(np.float32)
+    workers = max(1, min(8, os.cpu_count() or 1))
+    pending = []
+
+    def put(lo, hi, fut):
+        out[lo:hi] = fut.result()
+
+    with cf.ThreadPoolExecutor(workers) as ex:
+        for lo in range(0, m, _CHUNK):
+            hi = min(m, lo + _CHUNK)
+            c = hi - lo
+            if kind == "gmm_iso":
+                z, e = None, rng.standard_normal((c, d))
+            elif kind == "unit_lowrank":
+                z = rng.standard_normal((c, cfg["rank"]))
+                e = rng.normal(0.0, cfg.get("eps", 0.3), (c, d))
+            else:
+                z = rng.standard_normal((c, cfg["rank"]))
+                e = rng.normal(0.0, 1.0 if kind == "gmm_int" else cfg.get("eps", 0.01), (c, d))
+            pending.append((lo, hi, ex.submit(_chunk_values, cfg, p, labels[lo:hi], z, e)))
+            while len(pending) > workers:  # bound the chunks held in memory
+                put(*pending.pop(0))
+        for item in pending:
+            put(*item)
     return out
 
 

@@ -103,3 +103,21 @@ def test_validate_cached_graphs():
             pytest.skip("graph cache not built")
         g = cache.load(name, "graph")
         assert _validate(g) == 0
+
+
+@pytest.mark.parametrize("n,d,K", [(1, 8, 1), (100, 0, 5), (100, 8, 0), (100, 8, 101), (10, 8, 10),
+                                   ((1 << 25) + 1, 8, 5)])
+def test_knn_rejects_bad_shapes_on_host(n, d, K):
+    keep, p = _fake()
+    rc = _lib.lib().ssg_knn_graph(p, n, d, K, p, p, p, 1 << 40, None, None)
+    assert rc == _lib.SSG_EINVAL
+    assert "ssg_knn_graph" in _lib.last_error()
+
+
+def test_knn_rejects_small_or_misaligned_workspace():
+    keep, p = _fake()
+    need = _lib.lib().ssg_knn_workspace_bytes(1000, 32, 10)
+    assert need > 1000 * 32 * 4
+    assert _lib.lib().ssg_knn_graph(p, 1000, 32, 10, p, p, p, need - 1, None, None) == _lib.SSG_EINVAL
+    assert _lib.lib().ssg_knn_graph(p, 1000, 32, 10, p, p, p + 8, need, None, None) == _lib.SSG_EINVAL
+    assert _lib.lib().ssg_knn_workspace_bytes(1, 32, 10) == 0
