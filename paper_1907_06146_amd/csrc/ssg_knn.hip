@@ -40,6 +40,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "ssg.h"
 #include "ssg_internal.h"
@@ -51,9 +52,10 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;       // rows per workgroup
-constexpr int BN = 128;       // columns per tile
-constexpr int NT = 256;       // threads per workgroup (4 wavefronts, 2 x 2 of 64 x 64)
-constexpr int QCAP = 2048;    // LDS queue entries
+constexpr int BN = 64;        // columns per tile
+constexpr int NT = 256;       // threads per scan workgroup (4 wavefronts, 2 x 2 of 64 x 32)
+constexpr int NW = NT / 64;
+constexpr int QW = 1024;      // LDS queue entries per wavefront
 constexpr int KP_MAX = 128;   // candidate list length
 constexpr int MARGIN = 28;    // extra candidates kept in split mode
 constexpr int FB_ROWS = 256;  // fallback rows per launch
@@ -231,30 +233,46 @@ struct ScanArgs {
   int DP, KP;
 };
 
+// Wavefront w of a scan workgroup computes rows 64 * (w >> 1) + [0, 64) and
+// columns 32 * (w & 1) + [0, 32) of each 128 x 64 tile: 4 x 2 MFMA blocks
+// of 16 x 16. Two workgroups share a CU, so the two wavefronts on a SIMD
+// belong to different workgroups and their phases (matrix cores, threshold
+// tests, barriers) overlap. Lane l holds, for block (bi, bj), rows 16 bi + 4 (l >> 4) + i
+// (i < 4) of column 16 bj + (l & 15).
 template <bool SPLIT, int NKS>
 struct ScanSmem {
   static constexpr bool AREG = NKS > 0;              // A fragments held in registers
-  static constexpr int KC = AREG ? 32 * NKS : 64;    // dimensions per staged chunk
+  static constexpr int KC = AREG ? 32 * NKS : 32;    // dimensions per staged chunk
   static constexpr int SS = KC + 8;                  // LDS row stride (bf16): conflict-free 16-byte reads
   static constexpr int NB = SPLIT ? 2 : 1;
-  uint16_t sB[NB][BN * SS];
-  uint16_t sA[AREG ? 1 : NB][AREG ? 8 : BM * SS];
-  uint64_t q[QCAP];
-  uint64_t q2[QCAP];
-  uint64_t mt[4][2 * KP_MAX + 64];                   // per wavefront: list, output, new keys
+  struct Stage {
+    uint16_t sB[NB][BN * SS];
+    uint16_t sA[AREG ? 1 : NB][AREG ? 8 : BM * SS];
+  };
+  struct Merge {                                     // used only between tiles
+    uint64_t q2[NW * QW];                            // entries bucketed by row
+    uint64_t mt[NW][2 * KP_MAX + 64];                // per wavefront: list, output, new keys
+  };
+  union {
+    Stage st;
+    Merge mg;
+  };
+  uint64_t q[NW * QW];                               // one queue segment per wavefront
   uint32_t rowcnt[BM], rowoff[BM], rowfill[BM], lcnt[BM];
   float tau[BM];
-  uint32_t qcnt, flag;
+  uint32_t qn[NW];
+  uint32_t flag;
 };
 
-// Merges the queue into the per-row candidate lists; called by all threads.
+// Merges every wavefront's queue segment into the per-row candidate lists;
+// called by all threads. Leaves the segments empty.
 template <class SM>
 __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const uint32_t nq = min(sm.qcnt, (uint32_t)QCAP);
   for (int t = tid; t < BM; t += NT) { sm.rowcnt[t] = 0; sm.rowfill[t] = 0; }
   __syncthreads();
-  for (uint32_t e = tid; e < nq; e += NT) atomicAdd(&sm.rowcnt[(sm.q[e] >> 25) & 127u], 1u);
+  for (int e = tid; e < NW * QW; e += NT)
+    if ((uint32_t)(e % QW) < sm.qn[e / QW]) atomicAdd(&sm.rowcnt[(sm.q[e] >> 25) & 127u], 1u);
   __syncthreads();
   if (wave == 0) {  // exclusive prefix over 128 row counts, two per lane
     const uint32_t v0 = sm.rowcnt[2 * lane], v1 = sm.rowcnt[2 * lane + 1];
@@ -268,29 +286,42 @@ __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
     sm.rowoff[2 * lane + 1] = ex + v0;
   }
   __syncthreads();
-  for (uint32_t e = tid; e < nq; e += NT) {
+  for (int e = tid; e < NW * QW; e += NT) {
+    if ((uint32_t)(e % QW) >= sm.qn[e / QW]) continue;
     const uint64_t v = sm.q[e];
     const uint32_t r = (uint32_t)(v >> 25) & 127u;
-    sm.q2[sm.rowoff[r] + atomicAdd(&sm.rowfill[r], 1u)] = v;
+    sm.mg.q2[sm.rowoff[r] + atomicAdd(&sm.rowfill[r], 1u)] = v;
   }
   __syncthreads();
   const int KP = a.KP;
-  uint64_t* Lk = sm.mt[wave];
+  uint64_t* Lk = sm.mg.mt[wave];
   uint64_t* Ok = Lk + KP_MAX;
   uint64_t* Nk = Lk + 2 * KP_MAX;
-  for (int r = wave; r < BM; r += 4) {
+  // the next row's list is loaded while the current row is merged
+  uint64_t pre0 = 0, pre1 = 0;
+  auto fetch = [&](int r) {
+    if (r >= BM) return;
+    const uint32_t lc = sm.lcnt[r];
+    const uint64_t* gl = a.w.lists + (r0 + r) * KP_MAX;
+    if ((uint32_t)lane < lc) pre0 = gl[lane];
+    if ((uint32_t)lane + 64 < lc) pre1 = gl[lane + 64];
+  };
+  fetch(wave);
+  for (int r = wave; r < BM; r += NW) {
     const uint32_t cnt = sm.rowcnt[r];
+    uint32_t lc = sm.lcnt[r];
+    if ((uint32_t)lane < lc) Lk[lane] = pre0;
+    if ((uint32_t)lane + 64 < lc) Lk[lane + 64] = pre1;
+    fetch(r + NW);
     if (cnt == 0) continue;
     const uint32_t off = sm.rowoff[r];
-    uint32_t lc = sm.lcnt[r];
     uint64_t* gl = a.w.lists + (r0 + r) * KP_MAX;
-    for (uint32_t k = lane; k < lc; k += 64) Lk[k] = gl[k];
     wave_sync();
     for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
       const uint32_t m = min(64u, cnt - c0);
       uint64_t nk = ~0ull;
       if ((uint32_t)lane < m) {
-        const uint64_t v = sm.q2[off + c0 + lane];
+        const uint64_t v = sm.mg.q2[off + c0 + lane];
         nk = (v & 0xFFFFFFFF00000000ull) | (v & 0x1FFFFFFull);
       }
       uint32_t r1 = 0;
@@ -318,34 +349,18 @@ __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
     }
     wave_sync();
   }
+  if (tid < NW) sm.qn[tid] = 0;
   __syncthreads();
-  if (tid == 0) sm.qcnt = 0;
-  __syncthreads();
-}
-
-// Appends the surviving lanes' entries to the queue; returns whether this
-// lane's entry was stored (false for lanes that did not survive).
-template <class SM>
-__device__ __forceinline__ bool queue_push(SM& sm, bool surv, uint64_t entry, int lane) {
-  const uint64_t m = __ballot(surv);
-  if (m == 0) return false;
-  const int fl = __builtin_ctzll(m);
-  uint32_t base = 0;
-  if (lane == fl) base = atomicAdd(&sm.qcnt, (uint32_t)__popcll(m));
-  base = __builtin_amdgcn_readlane(base, fl);
-  const uint32_t pos = base + mbcnt64(m);
-  const bool ok = surv && pos < (uint32_t)QCAP;
-  if (ok) sm.q[pos] = entry;
-  return ok;
 }
 
 template <bool SPLIT, int NKS>
-__global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
+__global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
   using SM = ScanSmem<SPLIT, NKS>;
   constexpr bool AREG = SM::AREG;
   constexpr int KC = SM::KC, SS = SM::SS, NB = SM::NB;
   constexpr int KS = KC / 32;                    // MFMA k-steps per chunk
   constexpr int CPT = BN * KC / 8 / NT;          // 16-byte pieces per thread per staged operand
+  constexpr int BJ = 2;                          // 16-column MFMA blocks per wavefront
   __shared__ __align__(16) SM sm;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -356,12 +371,14 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
   const int nchunk = AREG ? 1 : DP / KC;
   const int64_t ntiles = (n + BN - 1) / BN;
   const uint16_t* xs[2] = {a.w.xh, a.w.xl};
+  uint64_t* qseg = sm.q + wave * QW;
 
   for (int t = tid; t < BM; t += NT) {
     sm.lcnt[t] = 0;
     sm.tau[t] = (r0 + t < n) ? INFINITY : -INFINITY;
   }
-  if (tid == 0) { sm.qcnt = 0; sm.flag = 0; }
+  if (tid < NW) sm.qn[tid] = 0;
+  if (tid == 0) sm.flag = 0;
 
   // A fragments of this wavefront's 64 rows (exact mode, all dimensions)
   bf16x8 areg[AREG ? NB : 1][4][AREG ? NKS : 1];
@@ -378,31 +395,52 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
   }
 
   // staged-operand registers (the next chunk is loaded while this one is used)
+  constexpr int CPA = AREG ? 1 : BM * KC / 8 / NT;  // A pieces per thread (staged path)
   u32x4 pb[NB][CPT];
-  u32x4 pa[AREG ? 1 : NB][AREG ? 1 : CPT];
+  u32x4 pa[AREG ? 1 : NB][CPA];
+  float nyn[BJ];  // squared norms of the prefetched tile's columns
   auto load_chunk = [&](int64_t tile, int chunk) {
     const int kc = chunk * KC;
+    if (chunk == 0) {
 #pragma unroll
-    for (int h = 0; h < NB; ++h)
+      for (int bj = 0; bj < BJ; ++bj) nyn[bj] = a.w.ny[tile * BN + 32 * wn + 16 * bj + (lane & 15)];
+    }
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int piece = tid + c * NT;
         const int rr = piece / (KC / 8), part = piece % (KC / 8);
         pb[h][c] = *reinterpret_cast<const u32x4*>(xs[h] + (tile * BN + rr) * DP + kc + part * 8);
-        if constexpr (!AREG)
-          pa[h][c] = *reinterpret_cast<const u32x4*>(xs[h] + (r0 + rr) * DP + kc + part * 8);
       }
+      if constexpr (!AREG) {
+#pragma unroll
+        for (int c = 0; c < CPA; ++c) {
+          const int piece = tid + c * NT;
+          const int rr = piece / (KC / 8), part = piece % (KC / 8);
+          pa[h][c] = *reinterpret_cast<const u32x4*>(xs[h] + (r0 + rr) * DP + kc + part * 8);
+        }
+      }
+    }
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int h = 0; h < NB; ++h)
+    for (int h = 0; h < NB; ++h) {
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int piece = tid + c * NT;
         const int rr = piece / (KC / 8), part = piece % (KC / 8);
-        *reinterpret_cast<u32x4*>(&sm.sB[h][rr * SS + part * 8]) = pb[h][c];
-        if constexpr (!AREG) *reinterpret_cast<u32x4*>(&sm.sA[h][rr * SS + part * 8]) = pa[h][c];
+        *reinterpret_cast<u32x4*>(&sm.st.sB[h][rr * SS + part * 8]) = pb[h][c];
       }
+      if constexpr (!AREG) {
+#pragma unroll
+        for (int c = 0; c < CPA; ++c) {
+          const int piece = tid + c * NT;
+          const int rr = piece / (KC / 8), part = piece % (KC / 8);
+          *reinterpret_cast<u32x4*>(&sm.st.sA[h][rr * SS + part * 8]) = pa[h][c];
+        }
+      }
+    }
   };
 
   load_chunk(0, 0);
@@ -412,17 +450,23 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
     for (int i = 0; i < 4; ++i) tr[bi * 4 + i] = sm.tau[64 * wm + 16 * bi + 4 * (lane >> 4) + i];
+  uint32_t qn = 0;  // entries in this wavefront's segment (uniform)
 
   for (int64_t tile = 0; tile < ntiles; ++tile) {
-    f32x4 acc[4][4];
+    f32x4 acc[4][BJ];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    float nyc[BJ];
     for (int chunk = 0; chunk < nchunk; ++chunk) {
       __syncthreads();  // previous chunk's readers are done with the LDS tiles
       store_chunk();
+      if (chunk == 0) {
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) nyc[bj] = nyn[bj];
+      }
       __syncthreads();
       {  // prefetch the next chunk (or the next tile's first chunk)
         int nc = chunk + 1;
@@ -432,14 +476,14 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
       }
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 bfr[NB][4];
+        bf16x8 bfr[NB][BJ];
         bf16x8 afr[NB][4];
 #pragma unroll
         for (int h = 0; h < NB; ++h)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj)
+          for (int bj = 0; bj < BJ; ++bj)
             bfr[h][bj] = *reinterpret_cast<const bf16x8*>(
-                &sm.sB[h][(64 * wn + 16 * bj + (lane & 15)) * SS + 32 * ks + 8 * (lane >> 4)]);
+                &sm.st.sB[h][(32 * wn + 16 * bj + (lane & 15)) * SS + 32 * ks + 8 * (lane >> 4)]);
 #pragma unroll
         for (int h = 0; h < NB; ++h)
 #pragma unroll
@@ -448,12 +492,12 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
               afr[h][bi] = areg[h][bi][ks];
             else
               afr[h][bi] = *reinterpret_cast<const bf16x8*>(
-                  &sm.sA[h][(64 * wm + 16 * bi + (lane & 15)) * SS + 32 * ks + 8 * (lane >> 4)]);
+                  &sm.st.sA[h][(64 * wm + 16 * bi + (lane & 15)) * SS + 32 * ks + 8 * (lane >> 4)]);
           }
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 4; ++bj) {
+          for (int bj = 0; bj < BJ; ++bj) {
             acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[0][bi], bfr[0][bj], acc[bi][bj], 0, 0, 0);
             if constexpr (SPLIT) {
               acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[0][bi], bfr[1][bj], acc[bi][bj], 0, 0, 0);
@@ -463,60 +507,91 @@ __global__ __launch_bounds__(NT) void knn_scan(ScanArgs a) {
       }
     }
 
-    // ---- epilogue: threshold test and queue append
+    // ---- epilogue: threshold test, append to this wavefront's segment
     const int64_t c0 = tile * BN;
-    float nyc[4];
+    const bool special = (c0 < r0 + BM && c0 + BN > r0) || c0 + BN > n;  // self pairs, absent columns
+    // Appends the selected elements that pass the threshold; returns those
+    // that found the segment full. SPECIAL tiles also drop self pairs and
+    // absent columns; SEL restricts the test to the elements set in sel.
+    const uint32_t rbase = (uint32_t)(64 * wm + 4 * (lane >> 4));
+    const uint32_t cbase = (uint32_t)(c0 + 32 * wn + (lane & 15));
+    const uint32_t n32 = (uint32_t)n, r032 = (uint32_t)r0;
+    auto push = [&](auto special_c, auto sel_c, uint64_t sel) -> uint64_t {
+      constexpr bool SPECIAL = decltype(special_c)::value;
+      constexpr bool SEL = decltype(sel_c)::value;
+      // branch-free pass: which 16 x 16 blocks hold a passing element
+      uint32_t blocks = 0;
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) nyc[bj] = a.w.ny[c0 + 64 * wn + 16 * bj + (lane & 15)];
-    const bool special = (tile == (int64_t)blockIdx.x) || (c0 + BN > n);
-    uint64_t pend = 0;
+      for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+        for (int bj = 0; bj < BJ; ++bj) {
+          uint64_t m = 0;
 #pragma unroll
-      for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int e = (bi * 4 + bj) * 4 + i;
-          const float s = fmaf(-2.f, acc[bi][bj][i], nyc[bj]);
-          const uint32_t rl = 64 * wm + 16 * bi + 4 * (lane >> 4) + i;
-          const int64_t col = c0 + 64 * wn + 16 * bj + (lane & 15);
-          bool surv = s <= tr[bi * 4 + i];
-          if (special) surv = surv && col < n && col != r0 + rl;
-          const uint64_t entry = ((uint64_t)ord_f32(s) << 32) | ((uint64_t)rl << 25) | (uint64_t)col;
-          const bool ok = queue_push(sm, surv, entry, lane);
-          if (surv && !ok) pend |= 1ull << e;
+          for (int i = 0; i < 4; ++i) m |= __ballot(fmaf(-2.f, acc[bi][bj][i], nyc[bj]) <= tr[bi * 4 + i]);
+          blocks |= (m != 0 ? 1u : 0u) << (bi * BJ + bj);
         }
-    if (__ballot(pend != 0) && lane == 0) sm.flag = 1;
+      uint64_t left = 0;
+      if (blocks == 0 && !SPECIAL) return left;
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) {
+          if (!SPECIAL && !((blocks >> (bi * BJ + bj)) & 1u)) continue;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = (bi * BJ + bj) * 4 + i;
+            const float s = fmaf(-2.f, acc[bi][bj][i], nyc[bj]);
+            bool surv = s <= tr[bi * 4 + i];
+            if constexpr (SEL) surv = surv && ((sel >> e) & 1ull);
+            const uint32_t rl = rbase + 16 * bi + i;
+            const uint32_t col = cbase + 16 * bj;
+            if constexpr (SPECIAL) surv = surv && col < n32 && col != r032 + rl;
+            const uint64_t m = __ballot(surv);
+            if (m) {
+              const uint32_t pos = qn + mbcnt64(m);
+              if (surv) {
+                if (pos < (uint32_t)QW)
+                  qseg[pos] = ((uint64_t)ord_f32(s) << 32) | ((uint64_t)rl << 25) | col;
+                else
+                  left |= 1ull << e;
+              }
+              qn = min(qn + (uint32_t)__popcll(m), (uint32_t)QW);
+            }
+          }
+        }
+      return left;
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    uint64_t pend = special ? push(T_{}, F_{}, 0ull) : push(F_{}, F_{}, 0ull);
+    // merge when a segment overflowed or has less room than one more tile's worst case
+    const bool need = __ballot(pend != 0) != 0 || qn > (uint32_t)(QW - 64);
+    if (lane == 0) {
+      sm.qn[wave] = qn;
+      if (need) sm.flag = 1;
+    }
     __syncthreads();
     while (sm.flag) {
-      merge_queue(sm, a, r0);  // ends with a barrier; empties the queue
+      merge_queue(sm, a, r0);  // ends with a barrier; empties the segments
+      qn = 0;
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int i = 0; i < 4; ++i) tr[bi * 4 + i] = sm.tau[64 * wm + 16 * bi + 4 * (lane >> 4) + i];
       if (tid == 0) sm.flag = 0;
       __syncthreads();
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int e = (bi * 4 + bj) * 4 + i;
-            const float s = fmaf(-2.f, acc[bi][bj][i], nyc[bj]);
-            const uint32_t rl = 64 * wm + 16 * bi + 4 * (lane >> 4) + i;
-            const int64_t col = c0 + 64 * wn + 16 * bj + (lane & 15);
-            const bool p = (pend >> e) & 1ull;
-            const bool surv = p && s <= tr[bi * 4 + i];
-            const uint64_t entry = ((uint64_t)ord_f32(s) << 32) | ((uint64_t)rl << 25) | (uint64_t)col;
-            const bool ok = queue_push(sm, surv, entry, lane);
-            if (p && (!surv || ok)) pend &= ~(1ull << e);
-          }
-      if (__ballot(pend != 0) && lane == 0) sm.flag = 1;
+      pend = special ? push(T_{}, T_{}, pend) : push(F_{}, T_{}, pend);  // now above the threshold: dropped
+      const bool again = __ballot(pend != 0) != 0;
+      if (lane == 0) {
+        sm.qn[wave] = qn;
+        if (again) sm.flag = 1;
+      }
       __syncthreads();
     }
   }
-  if (sm.qcnt > 0) merge_queue(sm, a, r0);  // qcnt was last written before a barrier
+  bool any = false;  // segments were published before the last barrier
+  for (int w = 0; w < NW; ++w) any |= sm.qn[w] > 0;
+  if (any) merge_queue(sm, a, r0);
   __syncthreads();
   for (int t = tid; t < BM; t += NT) a.w.lcnt[r0 + t] = sm.lcnt[t];
 }
