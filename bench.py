@@ -81,8 +81,9 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
-                    help="c2: the headline search; c4: mixed L/K batched form; c5: serving")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the headline search; c3: storage precisions on 960-d data; "
+                         "c4: mixed L/K batched form; c5: serving")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
     ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
@@ -100,6 +101,9 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload == "c3":
+        print(json.dumps(bench_precision_c3(a)), flush=True)
+        return
     if a.workload == "c4":
         print(json.dumps(bench_batched(a)), flush=True)
         return
@@ -400,6 +404,84 @@ def bench_batched(a):
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
     return out
+
+
+def bench_precision_c3(a):
+    """GIST-shaped 1M x 960 workload (values in [0, 1], squared L2), 1,000
+    queries, K = 10: FP32, BF16 and FP8-E4M3 storage (FP32 accumulation),
+    each with and without an FP32 rerank of the whole pool, at every swept
+    pool size: throughput, recall@10 and the error of the returned distances
+    against FP64 recomputation."""
+    import torch
+
+    from paper_1907_06146_amd import graph_io, quantize, search
+
+    t0 = time.time()
+    cfg, gc, base, q, gt = _load("c3")
+    log(f"c3 data ready in {time.time() - t0:.1f}s")
+    sweep = json.load(open(os.path.join(graph_io.default_root(), "c3", "sweep.json")))
+    orc = {r["L"]: r for r in sweep["rows"]}
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    tq = torch.from_numpy(q).to(dev)
+    K = cfg["K"]
+    nq, d = q.shape
+    stream = torch.cuda.current_stream()
+    codes = {"fp32": (tb, None)}
+    codes["bf16"] = quantize(tb, "bf16")
+    codes["fp8"] = quantize(tb, "fp8")
+    torch.cuda.synchronize()
+    elem = {"fp32": 4, "bf16": 2, "fp8": 1}
+    q64 = q.astype(np.float64)
+
+    def dist_err(ids, dd):
+        x = base[ids.reshape(-1)].astype(np.float64).reshape(nq, K, d)
+        ref = ((q64[:, None, :] - x) ** 2).sum(-1)
+        rel = np.abs(dd.astype(np.float64) - ref) / np.maximum(ref, 1e-30)
+        return float(rel.max()), float(rel.mean())
+
+    rows = []
+    for L in sorted(orc):
+        for fmt in ("fp32", "bf16", "fp8"):
+            for rr in ((False,) if fmt == "fp32" else (False, True)):
+                cb, sc = codes[fmt]
+                kw = dict(dim_scale=sc)
+                if rr:
+                    kw.update(base_f32=tb, rerank_k=L)
+                ids, dd, ndc, hops = search(cb, tg, te, tq, K, L, stats=True, **kw)
+                torch.cuda.synchronize()
+                ids_h = ids.cpu().numpy()
+                emax, emean = dist_err(ids_h, dd.cpu().numpy())
+                ms = _time(lambda: search(cb, tg, te, tq, K, L, **kw), a.steps, a.warmup, stream)
+                ndc_m = ndc.double().mean().item()
+                hops_m = hops.double().mean().item()
+                bq = algorithmic_bytes(ndc_m, hops_m, d, tg.shape[1], cfg["s"], K, elem[fmt]) \
+                    + (L * d * 4 if rr else 0)
+                row = {"L": L, "form": fmt + ("+fp32 rerank" if rr else ""),
+                       "recall10": recall_at(ids_h, gt, 10), "oracle_recall10": orc[L]["recall10"],
+                       "ms": ms, "qps": nq / ms * 1e3, "ndc": ndc_m, "hops": hops_m,
+                       "bytes_per_query": bq, "GBps": bq * nq / (ms / 1e3) / 1e9,
+                       "dist_rel_err_max": emax, "dist_rel_err_mean": emean}
+                rows.append(row)
+                log(row)
+    # steady state: the 1,000 queries tiled 16 times (one launch fills the device)
+    steady = {}
+    tq16 = tq.repeat(16, 1).contiguous()
+    Ls = 200
+    for fmt in ("fp32", "bf16", "fp8"):
+        cb, sc = codes[fmt]
+        kw = dict(dim_scale=sc)
+        if fmt != "fp32":
+            kw.update(base_f32=tb, rerank_k=Ls)
+        ms = _time(lambda: search(cb, tg, te, tq16, K, Ls, **kw), max(3, a.steps // 2), 1, stream)
+        steady[fmt] = {"L": Ls, "queries": int(tq16.shape[0]), "ms": ms, "qps": tq16.shape[0] / ms * 1e3}
+        log(f"steady {fmt}: {steady[fmt]}")
+    return {"metric": "queries/s and recall@10 per storage precision (GIST-shaped 1M x 960, 1 GPU)",
+            "unit": "queries/s", "n_gpus": 1, "workload": "gist-shaped synthetic 1,000,000 x 960 in "
+            "[0, 1], 1,000 queries, K = 10, squared L2", "rows": rows, "steady_state_16k": steady,
+            "data": "synthetic (seeded)"}
 
 
 def synth_cfg(name):

@@ -794,6 +794,7 @@ struct Table<F32T> {
           default: l.fn = pick_preg<F32T, 32, 4, 1>(preg, batched); return l; // 16
         }
       case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg, batched); return l;  // d = 300: 8
+      case 240: l.fn = pick_preg<F32T, 240, 32, 4>(preg, batched); return l;  // d = 960: 8
       default: break;
     }
     l.query_in_regs = false;
@@ -815,6 +816,7 @@ struct Table<BF16T> {
           case 4: l.query_in_regs = false; l.fn = pick_preg<BF16T, 16, 4, 1, true>(preg, batched); return l;
           default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;
         }
+      case 120: l.fn = pick_preg<BF16T, 120, 32, 4>(preg, batched); return l;  // d = 960: 8
       default: break;
     }
     l.query_in_regs = false;
@@ -829,6 +831,7 @@ struct Fp8Table {
     switch (dc) {
       case 6: l.fn = pick_preg<F, 6, 4, 1>(preg, batched); return l;  // d = 96
       case 8: l.fn = pick_preg<F, 8, 4, 1>(preg, batched); return l;  // d = 128
+      case 60: l.fn = pick_preg<F, 60, 32, 4>(preg, batched); return l;  // d = 960: 8
       default: break;
     }
     l.query_in_regs = false;

@@ -214,3 +214,38 @@ def test_c2_full_size_against_stored_oracle():
     assert np.array_equal(ghops, oh)
     gt = cache.load("c2", "gt_ids")
     assert core.recall_at(gi, gt, 10) >= 0.95
+
+
+@pytest.fixture(scope="module")
+def c3_full():
+    meta = cache.load_meta("c3")
+    if meta is None or not cache.exists("c3", "gt_ids"):
+        pytest.skip("1M x 960 cache not built")
+    cfg = synth.CONFIGS["c3"]
+    base = synth.base_vectors(cfg)
+    assert synth.checksum(base) == meta["base_sha"]
+    q = synth.queries(cfg, base)
+    return cfg, base, q, cache.load("c3", "graph"), cache.load("c3", "entry_ids")
+
+
+@pytest.mark.parametrize("L", [100, 400])
+def test_c3_full_size_against_stored_oracle(c3_full, L):
+    """GIST-shaped workload (1M x 960 floats in [0, 1], 1,000 queries, K = 10)
+    at the smallest and largest swept pool size, against the oracle's stored
+    results. Float data: a differing row must be explained by FP64 key ties
+    (the bar counts exact + explained rows), and recall@10 must match the
+    oracle's within 0.001."""
+    if not cache.exists("c3", f"oracle_L{L}_ids"):
+        pytest.skip(f"no stored oracle result at L={L}")
+    from parity_util import classify
+    cfg, base, q, g, entry = c3_full
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, cfg["K"], L)
+    oi = cache.load("c3", f"oracle_L{L}_ids")
+    exact, explained, genuine = classify(base, q, gi, oi, "l2")
+    print(f"c3 L={L}: exact {exact.mean():.4f} explained {explained.mean():.4f} "
+          f"genuine {genuine.mean():.4f}", flush=True)
+    assert (exact | explained).mean() >= 0.99
+    oh = cache.load("c3", f"oracle_L{L}_hops")
+    assert (ghops[exact] == oh[exact]).mean() >= 0.99
+    gt = cache.load("c3", "gt_ids")
+    assert abs(core.recall_at(gi, gt, 10) - core.recall_at(oi, gt, 10)) <= 0.001
