@@ -238,6 +238,40 @@ int ssg_knn_graph(const float* base, int64_t n, int32_t d, int32_t K, uint32_t* 
                   float* out_dists, void* workspace, size_t workspace_bytes, int64_t* stats,
                   void* stream);
 
+/*
+ * ssg_nssg_prune -- first loop of the indexing algorithm (Alg. 3): for every
+ * node i, candidates from the kNN graph and the SSG angular rule over them.
+ * Candidates: for each kNN neighbour u of i in ascending order, u and then
+ * u's whole kNN list (i and repeats skipped), stopping once at least l are
+ * held; candidates at distance 0 from i are dropped. They are taken in
+ * ascending (squared distance, id) order and one is kept unless a kept edge k
+ * has <c - i, k - i> > 0 and <c - i, k - i>^2 > cos2a |c - i|^2 |k - i|^2
+ * (Sec. 3.2's angle test, FP64, every operation rounded on its own).
+ *   base    DEVICE float32 n x d
+ *   knn     DEVICE uint32 n x Kk, rows ascending, padding SSG_SENTINEL
+ *   l, R    candidate target (l + Kk + 2 <= 1024) and out-degree (R <= 64)
+ *   cos2a   cos^2 of the minimum angle (0.25 for 60 degrees)
+ *   out     DEVICE uint32 n x R: kept ids in selection order, then padding
+ * Asynchronous on stream. SSG_EINVAL / SSG_EUNSUPPORTED for bad arguments.
+ */
+int ssg_nssg_prune(const float* base, int64_t n, int32_t d, const uint32_t* knn, int32_t Kk,
+                   int32_t l, int32_t R, double cos2a, uint32_t* out, void* stream);
+
+/*
+ * ssg_nssg_reverse -- second loop of Alg. 3 (reverse-neighbour checking),
+ * order-independent: node j re-selects, by the rule of ssg_nssg_prune, from
+ * its own out-edges (in order) plus every i with an edge i -> j that is not
+ * already one of them and is not at distance 0.
+ *   g1         DEVICE uint32 n x R from ssg_nssg_prune (ids, then padding)
+ *   out        DEVICE uint32 n x R (distinct from g1)
+ *   workspace  DEVICE, 256-byte aligned, ssg_nssg_reverse_workspace_bytes(n, R)
+ * Asynchronous on stream.
+ */
+size_t ssg_nssg_reverse_workspace_bytes(int64_t n, int32_t R);
+int ssg_nssg_reverse(const float* base, int64_t n, int32_t d, const uint32_t* g1, int32_t R,
+                     double cos2a, uint32_t* out, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
 

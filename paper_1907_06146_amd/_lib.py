@@ -1,7 +1,7 @@
 """ctypes binding of libssg (include/ssg.h). Argument marshalling only.
 
 Every step runs in the HIP kernels of ``csrc/ssg_search.hip`` (search) and
-``csrc/ssg_knn.hip`` (kNN graph).
+``csrc/ssg_knn.hip`` (kNN graph) and ``csrc/ssg_build.hip`` (graph pruning).
 There is no CPU or PyTorch fallback: if the shared library is missing or
 cannot be loaded, every call raises.
 """
@@ -25,7 +25,7 @@ EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_
            "ssg_validate_graph", "ssg_last_error", "ssg_version", "ssg_batch_workspace_bytes",
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
            "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
-           "ssg_knn_graph")
+           "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse")
 
 
 class SSGError(RuntimeError):
@@ -102,6 +102,13 @@ def lib() -> ctypes.CDLL:
             L.ssg_knn_workspace_bytes.restype = sz
             L.ssg_knn_graph.argtypes = [P, i64, i32, i32, P, P, P, sz, P, P]
             L.ssg_knn_graph.restype = ctypes.c_int
+            dbl = ctypes.c_double
+            L.ssg_nssg_prune.argtypes = [P, i64, i32, P, i32, i32, i32, dbl, P, P]
+            L.ssg_nssg_prune.restype = ctypes.c_int
+            L.ssg_nssg_reverse_workspace_bytes.argtypes = [i64, i32]
+            L.ssg_nssg_reverse_workspace_bytes.restype = sz
+            L.ssg_nssg_reverse.argtypes = [P, i64, i32, P, i32, dbl, P, P, sz, P]
+            L.ssg_nssg_reverse.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

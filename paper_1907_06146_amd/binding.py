@@ -137,3 +137,50 @@ def knn_graph(base, K: int, stream=None):
     del ws
     return ids, dd, {"exact_path": bool(stats[0]), "rescanned_rows": int(stats[1]),
                      "candidates": int(stats[2])}
+
+
+def cos2(alpha_deg: float) -> float:
+    """cos^2 of the minimum edge angle; exactly 0.25 at 60 degrees."""
+    import math
+    return 0.25 if alpha_deg == 60.0 else math.cos(math.radians(alpha_deg)) ** 2
+
+
+def nssg_prune(base, knn, l: int, R: int, alpha: float = 60.0, stream=None):
+    """First loop of Alg. 3 on the GPU: candidates from the kNN graph
+    (int32 [n, Kk], -1 padding) and the SSG angular rule; returns int32 [n, R]."""
+    _need_cuda("base", base, (torch.float32,))
+    _need_cuda("knn", knn, (torch.int32,))
+    n, d = base.shape
+    st = stream if stream is not None else torch.cuda.current_stream(base.device)
+    out = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    rc = _lib.lib().ssg_nssg_prune(_ptr(base), n, d, _ptr(knn), knn.shape[1], l, R, cos2(alpha),
+                                   _ptr(out), ctypes.c_void_p(st.cuda_stream))
+    _lib.check(rc)
+    return out
+
+
+def nssg_reverse(base, g1, alpha: float = 60.0, stream=None):
+    """Second loop of Alg. 3 (reverse-neighbour checking) on the GPU."""
+    _need_cuda("base", base, (torch.float32,))
+    _need_cuda("g1", g1, (torch.int32,))
+    n, d = base.shape
+    R = g1.shape[1]
+    st = stream if stream is not None else torch.cuda.current_stream(base.device)
+    L = _lib.lib()
+    nbytes = L.ssg_nssg_reverse_workspace_bytes(n, R)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=base.device)
+    off = (-ws.data_ptr()) % 256
+    out = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    rc = L.ssg_nssg_reverse(_ptr(base), n, d, _ptr(g1), R, cos2(alpha), _ptr(out),
+                            ctypes.c_void_p(ws.data_ptr() + off), nbytes, ctypes.c_void_p(st.cuda_stream))
+    _lib.check(rc)
+    st.synchronize()  # the workspace is released on return
+    return out
+
+
+def nssg_graph(base, knn_k: int, l: int, R: int, alpha: float = 60.0):
+    """kNN graph, forward pruning and reverse checking of Alg. 3, all on the
+    GPU. Returns (g2 int32 [n, R], kNN ids int32 [n, knn_k])."""
+    ids, _, _ = knn_graph(base, knn_k)
+    g1 = nssg_prune(base, ids, l, R, alpha)
+    return nssg_reverse(base, g1, alpha), ids

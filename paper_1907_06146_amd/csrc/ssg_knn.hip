@@ -43,6 +43,7 @@
 #include <type_traits>
 
 #include "ssg.h"
+#include "ssg_device.h"
 #include "ssg_internal.h"
 
 namespace {
@@ -103,29 +104,7 @@ __device__ __forceinline__ uint32_t lower_bound(const uint64_t* a, uint32_t cnt,
   return lo;
 }
 
-// Squared Euclidean distance in FP64, dimensions summed in order, every
-// operation rounded on its own (no fused multiply-add).
-__device__ double exact_l2(const float* __restrict__ a, const float* __restrict__ b, int d) {
-#pragma clang fp contract(off)
-  double s = 0.0;
-  int j = 0;
-  if (((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
-    for (; j + 4 <= d; j += 4) {
-      float4 x = *reinterpret_cast<const float4*>(a + j);
-      float4 y = *reinterpret_cast<const float4*>(b + j);
-      double t;
-      t = (double)x.x - (double)y.x; s = s + t * t;
-      t = (double)x.y - (double)y.y; s = s + t * t;
-      t = (double)x.z - (double)y.z; s = s + t * t;
-      t = (double)x.w - (double)y.w; s = s + t * t;
-    }
-  }
-  for (; j < d; ++j) {
-    double t = (double)a[j] - (double)b[j];
-    s = s + t * t;
-  }
-  return s;
-}
+using ssgdev::exact_l2;
 
 struct Ws {
   uint16_t* xh;        // [NP x DP] BF16 of the base, zero padded

@@ -121,3 +121,17 @@ def test_knn_rejects_small_or_misaligned_workspace():
     assert _lib.lib().ssg_knn_graph(p, 1000, 32, 10, p, p, p, need - 1, None, None) == _lib.SSG_EINVAL
     assert _lib.lib().ssg_knn_graph(p, 1000, 32, 10, p, p, p + 8, need, None, None) == _lib.SSG_EINVAL
     assert _lib.lib().ssg_knn_workspace_bytes(1, 32, 10) == 0
+
+
+def test_build_steps_reject_bad_arguments_on_host():
+    keep, p = _fake()
+    L = _lib.lib()
+    assert L.ssg_nssg_prune(p, 100, 8, p, 10, 20, 65, 0.25, p, None) == _lib.SSG_EINVAL  # R > 64
+    assert L.ssg_nssg_prune(p, 100, 8, p, 600, 500, 16, 0.25, p, None) == _lib.SSG_EUNSUPPORTED
+    assert L.ssg_nssg_prune(p, 100, 8, p, 10, 20, 16, 1.5, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_nssg_prune(None, 100, 8, p, 10, 20, 16, 0.25, p, None) == _lib.SSG_EINVAL
+    need = L.ssg_nssg_reverse_workspace_bytes(1000, 16)
+    assert need > 1000 * 16 * 4
+    assert L.ssg_nssg_reverse(p, 1000, 8, p, 16, 0.25, p, p, need - 1, None) == _lib.SSG_EINVAL
+    assert L.ssg_nssg_reverse(p, 1000, 8, p, 16, 0.25, p, p + 8, need, None) == _lib.SSG_EINVAL
+    assert "ssg_nssg_reverse" in _lib.last_error()
