@@ -81,9 +81,10 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build"],
                     help="c2: the headline search; c3: storage precisions on 960-d data; "
-                         "c4: mixed L/K batched form; c5: serving")
+                         "c4: mixed L/K batched form; c5: serving; build: GPU index build "
+                         "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
     ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
@@ -101,6 +102,9 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload == "build":
+        print(json.dumps(bench_build(a)), flush=True)
+        return
     if a.workload == "c3":
         print(json.dumps(bench_precision_c3(a)), flush=True)
         return
@@ -403,6 +407,63 @@ def bench_batched(a):
         log(f"{name}: {ms:.3f} ms, recall {r:.4f}, x{ms_plain / ms:.2f}")
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
+    return out
+
+
+def bench_build(a):
+    """Index build on the SIFT-shaped 1M x 128 integer set: exact kNN graph
+    (K = 100) on the matrix cores, then the forward and reverse pruning loops
+    of Alg. 3 (l = 100, R = 50, 60 degrees). The kNN scan is priced against the
+    dense BF16 matrix-core peak with the self-join's 2 n^2 d flops."""
+    import torch
+
+    import synth
+    from paper_1907_06146_amd.binding import knn_graph, nssg_prune, nssg_reverse
+
+    cfg = synth.CONFIGS["c2"]
+    base = synth.base_vectors(cfg)
+    n, d = base.shape
+    tb = torch.from_numpy(base).cuda()
+    times = {"knn": [], "prune": [], "reverse": []}
+    for rep in range(1 + max(1, a.steps // 10)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids, _, st = knn_graph(tb, cfg["knn_k"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g1 = nssg_prune(tb, ids, cfg["l"], cfg["R"], cfg["alpha"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        nssg_reverse(tb, g1, cfg["alpha"])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if rep == 0:
+            continue  # warm-up
+        times["knn"].append(t1 - t0)
+        times["prune"].append(t2 - t1)
+        times["reverse"].append(t3 - t2)
+        log(f"build rep {rep}: knn {t1 - t0:.3f}s prune {t2 - t1:.3f}s reverse {t3 - t2:.3f}s {st}")
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    flops = 2.0 * n * n * d
+    out = {"metric": "index build seconds (kNN graph + Alg. 3 pruning loops), 1 GPU",
+           "value": med["knn"] + med["prune"] + med["reverse"], "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "workload": "sift-shaped synthetic 1,000,000 x 128 integers, kNN K = 100, "
+           "l = 100, R = 50, alpha = 60 degrees", "stage_s": med, "exact_path": st["exact_path"],
+           "roofline_knn": {"bound": "mfma", "achieved": flops / med["knn"] / 1e12, "peak": 2500.0,
+                            "unit": "TFLOP/s", "frac": flops / med["knn"] / 1e12 / 2500.0,
+                            "note": "whole kNN call (prep, scan, rerank); 2 n^2 d flops"},
+           "data": "synthetic (seeded)"}
+    if not a.no_cpu:
+        from oracle import core
+        rows = np.random.default_rng(0).choice(n, 64, replace=False)
+        t0 = time.perf_counter()
+        core.bruteforce(base, base[rows], cfg["knn_k"], "l2", skip=rows)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dt / len(rows) * n, "unit": "s (kNN graph, extrapolated)",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle",
+                               "sample": f"{len(rows)} rows of the exact kNN graph by the oracle's "
+                                         f"FP64 full scan ({dt:.1f}s), scaled to {n} rows"}
     return out
 
 
