@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
     ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
+    ap.add_argument("--serve-mode", default="batch", choices=["batch", "request"],
+                    help="c5: continuous batching of waiting requests, or one launch per request")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: 3 launches of the timed configuration, then a 1 GiB "
                          "element-wise copy whose bytes calibrate the counters; no output")
@@ -553,11 +555,14 @@ def synth_cfg(name):
 def bench_serving(a):
     """Serving: 5M x 96 unit-norm base (BF16 search, FP32 rerank of K = 10)
     resident in HBM; Poisson arrivals of requests of 1..256 queries with one
-    L in {32..256}; continuous batching over 8 slots."""
+    L in {32..256}. Default: continuous batching (every waiting request joins
+    the next mixed batch, 3 batch slots); --serve-mode request launches each
+    request on its own (8 slots)."""
     import torch
 
     from paper_1907_06146_amd import graph_io, quantize
-    from paper_1907_06146_amd.serve import GpuDevice, Scheduler, poisson_requests, run, summarize
+    from paper_1907_06146_amd.serve import (BatchScheduler, GpuBatchDevice, GpuDevice, Scheduler,
+                                            poisson_requests, run, summarize)
 
     t0 = time.time()
     cfg, gc, base, q, gt = _load(a.serve_data)
@@ -572,12 +577,19 @@ def bench_serving(a):
     rng = np.random.default_rng(scfg["seed"] + 5)
     reqs, picks = poisson_requests(rng, a.requests, a.offered_rps, q, scfg["L_choices"], scfg["K"],
                                    max_batch=256)
-    n_slots = 8
-    gdev = GpuDevice(qb, tg, te, n_slots=n_slots, max_batch=256, max_K=scfg["K"], metric="ip",
-                     base_f32=tb, rerank=True)
     warm, _ = poisson_requests(np.random.default_rng(1), 50, 1e6, q, [64], scfg["K"], max_batch=64)
-    run(warm, Scheduler(gdev, n_slots, 4096))
-    sch = Scheduler(gdev, n_slots=n_slots, inflight_budget=6144)
+    if a.serve_mode == "batch":
+        n_slots, max_batch = 3, 8192
+        gdev = GpuBatchDevice(qb, tg, te, n_slots=n_slots, max_batch=max_batch, max_K=scfg["K"],
+                              metric="ip", base_f32=tb, rerank=True)
+        run(warm, BatchScheduler(gdev, n_slots, max_batch))
+        sch = BatchScheduler(gdev, n_slots=n_slots, max_batch=max_batch)
+    else:
+        n_slots = 8
+        gdev = GpuDevice(qb, tg, te, n_slots=n_slots, max_batch=256, max_K=scfg["K"], metric="ip",
+                         base_f32=tb, rerank=True)
+        run(warm, Scheduler(gdev, n_slots, 4096))
+        sch = Scheduler(gdev, n_slots=n_slots, inflight_budget=6144)
     done = run(reqs, sch)
     s = summarize(done)
     hit = 0.0
@@ -587,13 +599,14 @@ def bench_serving(a):
             hit += len(np.intersect1d(row[row >= 0], gt[qi, :10])) / 10.0
             nqs += 1
     s.update(recall10=hit / nqs, offered_rps=a.offered_rps,
-             offered_qps=a.offered_rps * np.mean([len(r.queries) for r in reqs]),
-             slots=n_slots, max_running=sch.max_running_seen)
+             offered_qps=float(a.offered_rps * np.mean([len(r.queries) for r in reqs])),
+             mode=a.serve_mode, slots=n_slots, max_running=sch.max_running_seen)
+    if a.serve_mode == "batch":
+        s.update(batches=sch.batches, max_batch_queries=sch.max_batch_seen)
     log(f"serving: {s}")
     return {"metric": "serving queries/s and p50/p99 latency (BF16 + FP32 rerank, 1 GPU)",
             "index": f"{a.serve_data}: {len(base)} x {base.shape[1]}", "value": s["qps"],
             "unit": "queries/s", "n_gpus": 1, **s}
-
 
 def cpu_baseline(base, gc, q, K, L, cfg, sample):
     """The FP64 CPU oracle (Alg. 1, all host threads) on a bounded sample of

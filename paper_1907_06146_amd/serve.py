@@ -9,8 +9,19 @@ device while new requests keep arriving. Each slot owns pinned host staging
 buffers and device buffers sized for the largest request, so the loop
 allocates nothing per request.
 
-The scheduler is independent of the device: ``GpuDevice`` launches through
-the library, ``FakeDevice`` (tests) completes requests after scripted times.
+Two ways to put requests on the device:
+
+* ``Scheduler`` + ``GpuDevice``: one launch per request, requests overlap on
+  per-slot streams;
+* ``BatchScheduler`` + ``GpuBatchDevice`` (continuous batching): whenever a
+  batch slot is free, every waiting request (FIFO, up to a query budget) is
+  launched together as one mixed batch through the persistent batched kernel,
+  each query with its own request's pool size L and result count K. This
+  keeps the device full with a few launches at a time instead of one launch
+  per request.
+
+The schedulers are independent of the device: the GPU devices launch through
+the library, the fake devices (tests) complete work after scripted times.
 Nothing here changes a query's result: a request's output is the same alone
 and in any mix.
 """
@@ -96,7 +107,62 @@ class Scheduler:
         return not self.running and not self.waiting
 
 
-def run(requests: list[Request], scheduler: Scheduler, clock=None, spin_sleep: float = 0.0):
+class BatchScheduler:
+    """Continuous batching: whenever one of ``n_slots`` batch slots is free,
+    the waiting requests are taken in arrival order while their queries fit
+    ``max_batch`` (a larger request goes alone) and launched as one batch."""
+
+    def __init__(self, device, n_slots: int, max_batch: int):
+        if n_slots < 1 or max_batch < 1:
+            raise ValueError("need at least one slot and a positive batch size")
+        self.dev = device
+        self.free = list(range(n_slots))[::-1]
+        self.max_batch = max_batch
+        self.running: dict[int, list[Request]] = {}
+        self.waiting: collections.deque[Request] = collections.deque()
+        self.done: list[Request] = []
+        self.batches = 0
+        self.max_running_seen = 0
+        self.max_batch_seen = 0
+
+    def submit(self, r: Request):
+        self.waiting.append(r)
+
+    def step(self, now: float) -> int:
+        changes = 0
+        for slot, reqs in list(self.running.items()):
+            if self.dev.poll(slot):
+                outs = self.dev.results(slot, reqs)
+                t = self.dev.now() if hasattr(self.dev, "now") else now
+                for r, (ids, dd) in zip(reqs, outs):
+                    r.ids, r.dists, r.finished = ids, dd, t
+                    self.done.append(r)
+                del self.running[slot]
+                self.free.append(slot)
+                changes += 1
+        while self.waiting and self.free:
+            batch = [self.waiting.popleft()]
+            total = len(batch[0].queries)
+            while self.waiting and total + len(self.waiting[0].queries) <= self.max_batch:
+                r = self.waiting.popleft()
+                batch.append(r)
+                total += len(r.queries)
+            slot = self.free.pop()
+            for r in batch:
+                r.slot, r.admitted = slot, now
+            self.running[slot] = batch
+            self.batches += 1
+            self.max_running_seen = max(self.max_running_seen, len(self.running))
+            self.max_batch_seen = max(self.max_batch_seen, total)
+            self.dev.launch_batch(slot, batch)
+            changes += 1
+        return changes
+
+    def idle(self) -> bool:
+        return not self.running and not self.waiting
+
+
+def run(requests: list[Request], scheduler, clock=None, spin_sleep: float = 0.0):
     """Feed requests at their arrival times and run the scheduler until every
     request has finished. ``clock`` returns seconds since the start."""
     if clock is None:
@@ -161,6 +227,27 @@ class FakeDevice:
         return np.tile(np.arange(K, dtype=np.int32), (b, 1)) + r.rid, np.zeros((b, K), np.float32)
 
 
+class FakeBatchDevice:
+    """Scripted batch device for scheduler tests: a batch finishes
+    ``cost(batch)`` seconds of simulated time after its launch."""
+
+    def __init__(self, cost, clock):
+        self.cost, self.clock = cost, clock
+        self.end: dict[int, float] = {}
+        self.launched: list[tuple[int, list[int]]] = []
+
+    def launch_batch(self, slot, reqs):
+        self.end[slot] = self.clock() + self.cost(reqs)
+        self.launched.append((slot, [r.rid for r in reqs]))
+
+    def poll(self, slot):
+        return self.clock() >= self.end[slot]
+
+    def results(self, slot, reqs):
+        return [(np.tile(np.arange(r.K, dtype=np.int32), (len(r.queries), 1)) + r.rid,
+                 np.zeros((len(r.queries), r.K), np.float32)) for r in reqs]
+
+
 class GpuDevice:
     """Slots backed by one stream each, pinned staging buffers and device
     buffers for up to ``max_batch`` queries; searches run in libssg."""
@@ -211,3 +298,110 @@ class GpuDevice:
         s = self.slots[slot]
         return (s["hi"].view(-1)[:b * K].view(b, K).numpy().copy(),
                 s["hd"].view(-1)[:b * K].view(b, K).numpy().copy())
+
+
+class GpuBatchDevice:
+    """Batch slots for ``BatchScheduler``: each slot owns a stream, pinned
+    staging buffers and device buffers for up to ``max_batch`` queries, and
+    runs a batch through the persistent batched kernel (``ssg_search_batched``)
+    with every query's own L and K; nothing is allocated per batch."""
+
+    def __init__(self, base, graph, entry_ids, n_slots: int, max_batch: int, max_K: int,
+                 metric: str = "l2", dim_scale=None, base_f32=None, rerank: bool = False,
+                 shapes=None):
+        import ctypes
+
+        import torch
+
+        from . import _lib
+        from .batched import BUCKET_BOUNDS
+        from .binding import _DTYPES, _METRICS
+        self.torch, self.ctypes, self.lib_mod = torch, ctypes, _lib
+        self.bounds = BUCKET_BOUNDS
+        self.index = (base, graph, entry_ids, dim_scale, base_f32)
+        self.dtype, self.metric = _DTYPES[base.dtype], _METRICS[metric]
+        self.rerank = -1 if rerank else 0
+        self.max_K, self.shapes = max_K, shapes or {}
+        dev = base.device
+        d = base.shape[1]
+        nbmax = len(BUCKET_BOUNDS)
+        wsb = _lib.lib().ssg_batch_workspace_bytes(nbmax)
+        self.slots = []
+        for _ in range(n_slots):
+            ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+            self.slots.append(dict(
+                stream=torch.cuda.Stream(device=dev),  # default priority
+                hq=torch.empty((max_batch, d), dtype=torch.float32, pin_memory=True),
+                hLK=torch.empty((3, max_batch), dtype=torch.int32, pin_memory=True),
+                dq=torch.empty((max_batch, d), dtype=torch.float32, device=dev),
+                dLK=torch.empty((3, max_batch), dtype=torch.int32, device=dev),
+                di=torch.empty((max_batch, max_K), dtype=torch.int32, device=dev),
+                dd=torch.empty((max_batch, max_K), dtype=torch.float32, device=dev),
+                hi=torch.empty((max_batch, max_K), dtype=torch.int32, pin_memory=True),
+                hd=torch.empty((max_batch, max_K), dtype=torch.float32, pin_memory=True),
+                ws=ws, wsp=(ws.data_ptr() + 255) & ~255, wsb=wsb,
+                ev=torch.cuda.Event(), b=0))
+
+    def launch_batch(self, slot, reqs):
+        from .batched import plan_buckets
+        torch, ctypes, _lib = self.torch, self.ctypes, self.lib_mod
+        s = self.slots[slot]
+        b = sum(len(r.queries) for r in reqs)
+        if b > s["hq"].shape[0] or any(r.K > self.max_K for r in reqs):
+            raise ValueError("batch larger than the slot buffers")
+        hq = s["hq"].numpy()
+        hLK = s["hLK"].numpy()
+        o = 0
+        for r in reqs:  # the slot's previous batch has completed (polled)
+            m = len(r.queries)
+            hq[o:o + m] = r.queries
+            hLK[0, o:o + m] = r.L
+            hLK[1, o:o + m] = r.K
+            o += m
+        plan = plan_buckets(hLK[0, :b], self.bounds)
+        o = 0
+        offs = []
+        for _, qi in plan:  # the bucket query lists share row 2
+            hLK[2, o:o + len(qi)] = qi
+            offs.append(o)
+            o += len(qi)
+        base, graph, entry, scale, bf32 = self.index
+        with torch.cuda.stream(s["stream"]):
+            s["dq"][:b].copy_(s["hq"][:b], non_blocking=True)
+            for k in range(3):
+                s["dLK"][k, :b].copy_(s["hLK"][k, :b], non_blocking=True)
+            dLK = s["dLK"]
+            desc = _lib.BatchDesc(
+                base.data_ptr(), base.shape[0], base.shape[1], self.dtype, self.metric,
+                None if scale is None else scale.data_ptr(),
+                None if bf32 is None else bf32.data_ptr(), self.rerank, graph.data_ptr(),
+                graph.shape[1], entry.data_ptr(), entry.numel(), s["dq"].data_ptr(), b,
+                dLK[0].data_ptr(), dLK[1].data_ptr(), self.max_K, s["di"].data_ptr(),
+                s["dd"].data_ptr(), None, None)
+            arr = (_lib.Bucket * len(plan))()
+            for i, ((mL, qi), off) in enumerate(zip(plan, offs)):
+                cap = next(x for x in self.bounds if mL <= x)
+                sh = self.shapes.get(cap, {})
+                arr[i] = _lib.Bucket(dLK[2].data_ptr() + 4 * off, len(qi), mL,
+                                     sh.get("gather_variant", 0), sh.get("hash_log2", 0),
+                                     sh.get("waves_per_block", 0), sh.get("blocks", 0))
+            _lib.check(_lib.lib().ssg_search_batched(ctypes.byref(desc), arr, len(plan),
+                                                     ctypes.c_void_p(s["wsp"]), s["wsb"],
+                                                     ctypes.c_void_p(s["stream"].cuda_stream)))
+            s["hi"][:b].copy_(s["di"][:b], non_blocking=True)
+            s["hd"][:b].copy_(s["dd"][:b], non_blocking=True)
+            s["ev"].record(s["stream"])
+        s["b"] = b
+
+    def poll(self, slot):
+        return self.slots[slot]["ev"].query()
+
+    def results(self, slot, reqs):
+        s = self.slots[slot]
+        hi, hd = s["hi"].numpy(), s["hd"].numpy()
+        out, o = [], 0
+        for r in reqs:
+            m = len(r.queries)
+            out.append((hi[o:o + m, :r.K].copy(), hd[o:o + m, :r.K].copy()))
+            o += m
+        return out

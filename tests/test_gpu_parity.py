@@ -249,3 +249,31 @@ def test_c3_full_size_against_stored_oracle(c3_full, L):
     assert (ghops[exact] == oh[exact]).mean() >= 0.99
     gt = cache.load("c3", "gt_ids")
     assert abs(core.recall_at(gi, gt, 10) - core.recall_at(oi, gt, 10)) <= 0.001
+
+
+def test_c5_full_size_against_stored_oracle():
+    """Serving index (5M x 96 unit-norm, inner product, 100,000 queries of which
+    5,000 are base points) at L = 96 against the oracle's stored results:
+    differing rows must be explained by FP64 key ties, and recall@10 must
+    match the oracle's within 0.001."""
+    meta = cache.load_meta("c5")
+    if meta is None or not cache.exists("c5", "oracle_L96_ids"):
+        pytest.skip("5M x 96 cache not built")
+    from parity_util import classify
+    cfg = synth.CONFIGS["c5"]
+    base = synth.base_vectors(cfg)
+    assert synth.checksum(base) == meta["base_sha"]
+    q = synth.queries(cfg, base)
+    g = cache.load("c5", "graph")
+    entry = cache.load("c5", "entry_ids")
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, cfg["K"], 96, "ip")
+    oi = cache.load("c5", "oracle_L96_ids")
+    exact, explained, genuine = classify(base, q, gi, oi, "ip")
+    print(f"c5 L=96: exact {exact.mean():.5f} explained {explained.mean():.5f} "
+          f"genuine {genuine.mean():.5f}", flush=True)
+    assert (exact | explained).mean() >= 0.999
+    gt = cache.load("c5", "gt_ids")
+    assert abs(core.recall_at(gi, gt, 10) - core.recall_at(oi, gt, 10)) <= 0.001
+    # indexed queries (the last 5,000 rows) find themselves first
+    ids = synth.indexed_query_ids(cfg)
+    assert (gi[-len(ids):, 0] == ids).mean() >= 0.99

@@ -73,3 +73,33 @@ def test_poisson_generator():
 def test_bad_configuration():
     with pytest.raises(ValueError):
         Scheduler(FakeDevice(lambda r: 0, SimClock()), 0, 10)
+
+
+def test_batch_scheduler_groups_waiting_requests():
+    from paper_1907_06146_amd.serve import BatchScheduler, FakeBatchDevice
+    clk = SimClock()
+    dev = FakeBatchDevice(lambda reqs: 0.002, clk)
+    sch = BatchScheduler(dev, n_slots=2, max_batch=64)
+    # a burst of requests at t = 0, then stragglers
+    sizes = [10, 20, 30, 40, 5, 100, 7, 3]
+    arrivals = [0.0] * 6 + [0.01, 0.01]
+    reqs = _reqs(sizes, arrivals)
+    done = run(reqs, sch, clock=clk)
+    assert len(done) == len(reqs)
+    batches = [rids for _, rids in dev.launched]
+    flat = [rid for b in batches for rid in b]
+    assert flat == sorted(flat)  # arrival order kept across batches
+    for b in batches:  # each batch fits the budget unless it is one oversized request
+        tot = sum(sizes[i] for i in b)
+        assert tot <= 64 or len(b) == 1
+    assert [5] in batches  # the 100-query request ran alone
+    assert sch.max_running_seen <= 2
+    for r in done:
+        assert r.arrival <= r.admitted <= r.finished
+        assert (r.ids == np.arange(4) + r.rid).all() and r.ids.shape == (len(r.queries), 4)
+
+
+def test_batch_scheduler_rejects_bad_sizes():
+    from paper_1907_06146_amd.serve import BatchScheduler, FakeBatchDevice
+    with pytest.raises(ValueError):
+        BatchScheduler(FakeBatchDevice(lambda r: 0.0, SimClock()), n_slots=0, max_batch=8)
