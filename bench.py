@@ -81,10 +81,12 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build", "sharded"],
                     help="c2: the headline search; c3: storage precisions on 960-d data; "
                          "c4: mixed L/K batched form; c5: serving; build: GPU index build "
-                         "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set")
+                         "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set; sharded: "
+                         "partitioned search over random shards on the 1M x 128 set")
+    ap.add_argument("--shards", type=int, default=4, help="sharded: number of shards")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
     ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
@@ -104,6 +106,9 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload == "sharded":
+        print(json.dumps(bench_sharded(a)), flush=True)
+        return
     if a.workload == "build":
         print(json.dumps(bench_build(a)), flush=True)
         return
@@ -410,6 +415,80 @@ def bench_batched(a):
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
     return out
+
+
+def bench_sharded(a):
+    """Partitioned search (Sec. 6.5) on the SIFT-shaped 1M x 128 set: S random
+    shards, each with an NSSG built on the GPU (exact kNN graph, forward and
+    reverse pruning; no DFS spanning), the 10,000 queries searched in every
+    shard (K = 100 per shard) and merged on the device; for each swept L the
+    recall@10 and throughput, against the one-graph FP32 search at the
+    oracle's operating point."""
+    import torch
+
+    import synth
+    from paper_1907_06146_amd import graph_io, search
+    from paper_1907_06146_amd.binding import knn_graph, nssg_prune, nssg_reverse
+    from paper_1907_06146_amd.sharded import ShardedIndex, partition
+
+    cfg, gc, base, q, gt = _load("c2")
+    sweep = json.load(open(os.path.join(graph_io.default_root(), "c2", "sweep.json")))
+    L1 = sweep["L_op"] or cfg["L"]
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tq = torch.from_numpy(q).to(dev)
+    stream = torch.cuda.current_stream()
+    K = cfg["K"]
+    nq = len(q)
+    # one-graph baseline
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    one_ms = _time(lambda: search(tb, tg, te, tq, K, L1), a.steps, a.warmup, stream)
+    one_ids, _ = search(tb, tg, te, tq, K, L1)
+    torch.cuda.synchronize()
+    one = {"L": L1, "ms": one_ms, "qps": nq / one_ms * 1e3, "recall10": recall_at(one_ids.cpu().numpy(), gt, 10)}
+    log(f"one graph: {one}")
+    # shards, built on the GPU
+    S = a.shards
+    parts = partition(len(base), S, seed=cfg["seed"] + 21)
+    bases, graphs, entries = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_, gids in enumerate(parts):
+        bs = tb.index_select(0, torch.from_numpy(gids).to(dev)).contiguous()
+        knn, _, _ = knn_graph(bs, cfg["knn_k"])
+        g2 = nssg_reverse(bs, nssg_prune(bs, knn, cfg["l"], cfg["R"], cfg["alpha"]), cfg["alpha"])
+        e = np.random.default_rng(cfg["seed"] + 31 + s_).choice(len(gids), cfg["s"], replace=False)
+        bases.append(bs)
+        graphs.append(g2)
+        entries.append(torch.from_numpy(e.astype(np.int32)).to(dev))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"{S} shard graphs built on the GPU in {build_s:.2f}s")
+    idx = ShardedIndex(bases, graphs, entries, parts)  # one launch over all shards
+    per_shard = ShardedIndex(bases, graphs, entries, parts, combined=False)
+    rows = []
+    best = None
+    for L in (20, 30, 40, 50, 60, 80, 100):
+        ids, _ = idx.search(tq, K, L)
+        ids2, _ = per_shard.search(tq, K, L)
+        torch.cuda.synchronize()
+        r10 = recall_at(ids.cpu().numpy(), gt, 10)
+        same = bool(torch.equal(ids, ids2))
+        ms = _time(lambda: idx.search(tq, K, L), a.steps, a.warmup, stream)
+        ms2 = _time(lambda: per_shard.search(tq, K, L), max(2, a.steps // 2), 1, stream)
+        row = {"L": L, "recall10": r10, "ms": ms, "qps": nq / ms * 1e3,
+               "ms_launch_per_shard": ms2, "same_ids_both_modes": same}
+        rows.append(row)
+        log(f"sharded S={S}: {row}")
+        if best is None and r10 >= 0.95:
+            best = row
+    return {"metric": "partitioned search queries/s at recall@10 >= 0.95 (1M x 128, 1 GPU)",
+            "value": best["qps"] if best else None, "unit": "queries/s", "n_gpus": 1,
+            "workload": f"sift-shaped synthetic 1,000,000 x 128, {S} random shards, 10,000 "
+                        f"queries, K = 100 per shard, merged to 100", "shards": S,
+            "shard_build_s": build_s, "rows": rows, "chosen": best, "one_graph": one,
+            "vs_one_graph": (best["qps"] / one["qps"]) if best else None, "data": "synthetic (seeded)"}
 
 
 def bench_build(a):

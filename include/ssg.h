@@ -73,6 +73,13 @@ typedef struct {
                                  results are written (precision form: search on
                                  BF16/FP8, rerank in FP32); NULL = no rerank */
     int32_t rerank_k;         /* entries to rerank, 0 = K; capped at L */
+    int64_t entry_group_size; /* > 0: queries form consecutive groups of this
+                                 many, and group g starts from the n_entry ids
+                                 entry_ids[g * n_entry ...] (entry_ids then
+                                 holds ceil(nq / size) sets); used to search
+                                 several shards' graphs, stored as one
+                                 block-diagonal graph, in one launch;
+                                 0 = every query uses the same n_entry ids */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144
@@ -271,6 +278,24 @@ size_t ssg_nssg_reverse_workspace_bytes(int64_t n, int32_t R);
 int ssg_nssg_reverse(const float* base, int64_t n, int32_t d, const uint32_t* g1, int32_t R,
                      double cos2a, uint32_t* out, void* workspace, size_t workspace_bytes,
                      void* stream);
+
+/*
+ * ssg_merge_shards -- aggregation step of the partitioned search (Sec. 6.5:
+ * the data set split at random into S shards, one graph per shard, every
+ * query searched in all of them): merges each query's S result lists into
+ * the first K_out by (distance, global id).
+ *   ids, dists  DEVICE [S][nq][K] per-shard results (shard-local ids,
+ *               SSG_SENTINEL / +inf padding), e.g. S ssg_search outputs
+ *               written into consecutive slices
+ *   id_map      DEVICE uint32: shard s's local id l is id_map[map_off[s] + l]
+ *   map_off     DEVICE int64[S]
+ *   out_ids, out_dists  DEVICE [nq][K_out]; padding where fewer than K_out
+ *               real results exist
+ * Requires S * K <= 4096 and K_out <= S * K. Asynchronous on stream.
+ */
+int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t S, int64_t nq, int32_t K,
+                     const uint32_t* id_map, const int64_t* map_off, int32_t K_out,
+                     uint32_t* out_ids, float* out_dists, void* stream);
 
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);

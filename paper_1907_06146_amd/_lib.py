@@ -1,7 +1,8 @@
 """ctypes binding of libssg (include/ssg.h). Argument marshalling only.
 
 Every step runs in the HIP kernels of ``csrc/ssg_search.hip`` (search) and
-``csrc/ssg_knn.hip`` (kNN graph) and ``csrc/ssg_build.hip`` (graph pruning).
+``csrc/ssg_knn.hip`` (kNN graph), ``csrc/ssg_build.hip`` (graph pruning) and
+``csrc/ssg_merge.hip`` (partitioned-search aggregation).
 There is no CPU or PyTorch fallback: if the shared library is missing or
 cannot be loaded, every call raises.
 """
@@ -25,7 +26,8 @@ EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_
            "ssg_validate_graph", "ssg_last_error", "ssg_version", "ssg_batch_workspace_bytes",
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
            "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
-           "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse")
+           "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse",
+           "ssg_merge_shards")
 
 
 class SSGError(RuntimeError):
@@ -38,7 +40,8 @@ class SearchOpts(ctypes.Structure):
     _fields_ = [("exact_visited", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
                 ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
-                ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32)]
+                ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32),
+                ("entry_group_size", ctypes.c_int64)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -109,6 +112,8 @@ def lib() -> ctypes.CDLL:
             L.ssg_nssg_reverse_workspace_bytes.restype = sz
             L.ssg_nssg_reverse.argtypes = [P, i64, i32, P, i32, dbl, P, P, sz, P]
             L.ssg_nssg_reverse.restype = ctypes.c_int
+            L.ssg_merge_shards.argtypes = [P, P, i32, i64, i32, P, P, i32, P, P, P]
+            L.ssg_merge_shards.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

@@ -33,7 +33,7 @@ def _need_cuda(name, t, dtypes=None):
 def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
            waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0,
-           base_f32=None, rerank_k: int = 0, out=None, stream=None):
+           base_f32=None, rerank_k: int = 0, out=None, stream=None, entry_group_size: int = 0):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -44,6 +44,9 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     with stats=True, also (ndc [nq] int32, hops [nq] int32).
     base_f32   optional [n, d] float32: rerank the first rerank_k (0 = K) pool
                entries exactly in FP32 before writing the K results.
+    entry_group_size  > 0: entry_ids is [G, s] and queries g*size .. (g+1)*size-1
+               start from row g (several shards stored as one block-diagonal
+               graph, searched in one launch).
     """
     _need_cuda("base", base, tuple(_DTYPES))
     _need_cuda("graph", graph, (torch.int32, torch.uint32))
@@ -74,14 +77,20 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     if stats:
         ndc = torch.empty(nq, dtype=torch.int32, device=dev)
         hops = torch.empty(nq, dtype=torch.int32, device=dev)
+    n_entry = entry_ids.numel()
+    if entry_group_size > 0:
+        if entry_ids.dim() != 2 or entry_ids.shape[0] * entry_group_size < nq:
+            raise ValueError("entry_group_size needs entry_ids of shape [groups, s] covering every query")
+        n_entry = entry_ids.shape[1]
     opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
                            None if ndc is None else ndc.data_ptr(),
                            None if hops is None else hops.data_ptr(), gather_variant,
-                           None if base_f32 is None else base_f32.data_ptr(), rerank_k)
+                           None if base_f32 is None else base_f32.data_ptr(), rerank_k,
+                           entry_group_size)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,
-        _ptr(graph), graph.shape[1], _ptr(entry_ids), entry_ids.numel(), _ptr(queries), nq, K, L,
+        _ptr(graph), graph.shape[1], _ptr(entry_ids), n_entry, _ptr(queries), nq, K, L,
         _METRICS[metric], _ptr(ids), _ptr(dd), ctypes.byref(opts), ctypes.c_void_p(st.cuda_stream))
     _lib.check(rc)
     if stats:

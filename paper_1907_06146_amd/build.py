@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", "ssg_search.hip"), os.path.join(HERE, "csrc", "ssg_knn.hip"),
-           os.path.join(HERE, "csrc", "ssg_build.hip")]
+           os.path.join(HERE, "csrc", "ssg_build.hip"),
+           os.path.join(HERE, "csrc", "ssg_merge.hip")]
 OUT = os.path.join(HERE, "libssg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

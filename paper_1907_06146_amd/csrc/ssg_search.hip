@@ -208,6 +208,7 @@ struct Args {
   const int32_t* K_arr;   // per-query result count, or null (K)
   int32_t kstride;        // output row stride (>= every K)
   uint32_t* counter;      // persistent work queue head, or null (one query per wave)
+  int64_t entry_group;    // > 0: query i uses entry[(i / entry_group) * s ...]; 0: all share
 };
 
 // ------------------------------------------------------------------ kernel
@@ -398,7 +399,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     uint64_t best = kNoKey;
     for (int e0 = 0; e0 < a.s; e0 += 64) {
       const int m = min(64, a.s - e0);
-      if (lane < m) bids[lane] = a.entry[e0 + lane];
+      if (lane < m) bids[lane] = a.entry[(a.entry_group > 0 ? qid / a.entry_group * a.s : 0) + e0 + lane];
       wave_sync();
       batch_keys(m);
       if (lane < m) best = min(best, bkeys[lane]);
@@ -993,6 +994,8 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.K_arr = nullptr;
   a.kstride = K;
   a.counter = nullptr;
+  if (o.entry_group_size < 0) return fail(SSG_EINVAL, "entry_group_size must be >= 0");
+  a.entry_group = o.entry_group_size;
   a.exact = o.exact_visited ? 1 : 0;
   a.base_f32 = o.base_f32;
   a.rerank = 0;

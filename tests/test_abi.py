@@ -135,3 +135,13 @@ def test_build_steps_reject_bad_arguments_on_host():
     assert L.ssg_nssg_reverse(p, 1000, 8, p, 16, 0.25, p, p, need - 1, None) == _lib.SSG_EINVAL
     assert L.ssg_nssg_reverse(p, 1000, 8, p, 16, 0.25, p, p + 8, need, None) == _lib.SSG_EINVAL
     assert "ssg_nssg_reverse" in _lib.last_error()
+
+
+def test_merge_shards_rejects_bad_arguments_on_host():
+    keep, p = _fake()
+    L = _lib.lib()
+    assert L.ssg_merge_shards(p, p, 0, 10, 5, p, p, 5, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(p, p, 50, 10, 100, p, p, 5, p, p, None) == _lib.SSG_EUNSUPPORTED
+    assert L.ssg_merge_shards(p, p, 2, 10, 5, p, p, 11, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(None, p, 2, 10, 5, p, p, 5, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(None, None, 2, 0, 5, None, None, 5, None, None, None) == _lib.SSG_OK
