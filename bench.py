@@ -81,11 +81,13 @@ def main():
     ap.add_argument("--hash-log2", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build", "sharded"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build", "sharded", "alpha",
+                                                        "scaling"],
                     help="c2: the headline search; c3: storage precisions on 960-d data; "
                          "c4: mixed L/K batched form; c5: serving; build: GPU index build "
                          "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set; sharded: "
-                         "partitioned search over random shards on the 1M x 128 set")
+                         "partitioned search over random shards on the 1M x 128 set; alpha: "
+                         "minimum-angle sweep; scaling: build and search cost against n")
     ap.add_argument("--shards", type=int, default=4, help="sharded: number of shards")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
@@ -106,6 +108,9 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload in ("alpha", "scaling"):
+        print(json.dumps(bench_alpha(a) if a.workload == "alpha" else bench_scaling(a)), flush=True)
+        return
     if a.workload == "sharded":
         print(json.dumps(bench_sharded(a)), flush=True)
         return
@@ -415,6 +420,124 @@ def bench_batched(a):
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
     return out
+
+
+def _gpu_nssg(tb, knn, cfg, alpha):
+    """Forward and reverse pruning on the GPU plus s random navigating nodes
+    (no DFS spanning); returns (graph, entry ids, prune + reverse seconds)."""
+    import torch
+
+    from paper_1907_06146_amd.binding import nssg_prune, nssg_reverse
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = nssg_reverse(tb, nssg_prune(tb, knn, cfg["l"], cfg["R"], alpha), alpha)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = np.random.default_rng(cfg["seed"] + 41).choice(tb.shape[0], cfg["s"], replace=False)
+    return g, torch.from_numpy(e.astype(np.int32)).to(tb.device), dt
+
+
+def _first_L(fn, Ls, target):
+    """Smallest L whose recall reaches target: returns (L, recall, extra) or the last row."""
+    last = None
+    for L in Ls:
+        r, extra = fn(L)
+        last = (L, r, extra)
+        if r >= target:
+            return last
+    return last
+
+
+def bench_alpha(a):
+    """Minimum-angle sweep (the paper's angle experiment) on the SIFT-shaped
+    1M x 128 set: one exact kNN graph, then an NSSG per angle built on the
+    GPU; for each angle the average out-degree and, at the smallest swept L
+    with recall@10 >= 0.95, the distance computations, hops and throughput of
+    the FP32 search (10,000 queries, K = 100)."""
+    import torch
+
+    from paper_1907_06146_amd import search
+    from paper_1907_06146_amd.binding import knn_graph
+
+    cfg, gc, base, q, gt = _load("c2")
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tq = torch.from_numpy(q).to(dev)
+    stream = torch.cuda.current_stream()
+    knn, _, _ = knn_graph(tb, cfg["knn_k"])
+    rows = []
+    for alpha in (40.0, 45.0, 50.0, 55.0, 60.0, 65.0, 70.0):
+        g, e, dt = _gpu_nssg(tb, knn, cfg, alpha)
+        aod = float((g >= 0).sum().item()) / len(base)
+
+        def at(L):
+            ids, _, ndc, hops = search(tb, g, e, tq, cfg["K"], L, stats=True)
+            torch.cuda.synchronize()
+            return recall_at(ids.cpu().numpy(), gt, 10), (ndc.double().mean().item(), hops.double().mean().item())
+        L, r, (ndc, hops) = _first_L(at, range(40, 241, 10), 0.95)
+        ms = _time(lambda: search(tb, g, e, tq, cfg["K"], L), a.steps, a.warmup, stream)
+        row = {"alpha": alpha, "aod": aod, "prune_reverse_s": dt, "L": L, "recall10": r, "ndc": ndc,
+               "hops": hops, "ms": ms, "qps": len(q) / ms * 1e3}
+        rows.append(row)
+        log(f"alpha {alpha}: {row}")
+    return {"metric": "search cost per minimum angle at recall@10 >= 0.95 (1M x 128, 1 GPU)",
+            "workload": "sift-shaped synthetic 1,000,000 x 128, NSSG l = 100, R = 50 built on the GPU "
+                        "(no DFS spanning), 10,000 queries, K = 100", "rows": rows,
+            "data": "synthetic (seeded)"}
+
+
+def bench_scaling(a):
+    """Build and search cost against n (the paper's complexity experiment):
+    prefixes of the SIFT-shaped set (the order is random) from 62,500 to
+    1,000,000 points, each indexed on the GPU (kNN graph, then forward and
+    reverse pruning = edge selection), and searched with the 10,000 queries at
+    the smallest L reaching recall@10 >= 0.99 against each prefix's exact top 10
+    (from an FP64 GPU matrix product; exact for these integer vectors)."""
+    import torch
+
+    from paper_1907_06146_amd import search
+    from paper_1907_06146_amd.binding import knn_graph
+
+    cfg, gc, base, q, gt_full = _load("c2")
+    dev = torch.device("cuda:0")
+    tq = torch.from_numpy(q).to(dev)
+    qn = (tq.double() ** 2).sum(1, keepdim=True)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in (62_500, 125_000, 250_000, 500_000, 1_000_000):
+        tb = torch.from_numpy(base[:n]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        knn, _, _ = knn_graph(tb, cfg["knn_k"])
+        torch.cuda.synchronize()
+        t_knn = time.perf_counter() - t0
+        g, e, t_edge = _gpu_nssg(tb, knn, cfg, cfg["alpha"])
+        # exact top 10 of each query over the prefix (integer data: every FP64
+        # sum is exact), ties by id
+        gt = np.empty((len(q), 10), np.int64)
+        tb64 = tb.double()
+        xn = (tb64 ** 2).sum(1)
+        for lo in range(0, len(q), 1000):
+            dd = qn[lo:lo + 1000] + xn[None, :] - 2.0 * (tq[lo:lo + 1000].double() @ tb64.t())
+            key = dd * (n + 1) + torch.arange(n, device=dev, dtype=torch.float64)[None, :]
+            gt[lo:lo + 1000] = torch.topk(key, 10, dim=1, largest=False).indices.cpu().numpy()
+
+        def at(L):
+            ids, _, ndc, hops = search(tb, g, e, tq, cfg["K"], L, stats=True)
+            torch.cuda.synchronize()
+            return recall_at(ids.cpu().numpy(), gt, 10), (ndc.double().mean().item(), hops.double().mean().item())
+        L, r, (ndc, hops) = _first_L(at, (20, 30, 40, 60, 80, 100, 120, 160, 200, 240, 300), 0.99)
+        ms = _time(lambda: search(tb, g, e, tq, cfg["K"], L), a.steps, a.warmup, stream)
+        row = {"n": n, "knn_s": t_knn, "edge_selection_s": t_edge, "L": L, "recall10": r, "ndc": ndc,
+               "hops": hops, "ms": ms, "qps": len(q) / ms * 1e3,
+               "aod": float((g >= 0).sum().item()) / n}
+        rows.append(row)
+        log(f"n {n}: {row}")
+        del tb, tb64, knn, g
+    return {"metric": "index build and search cost against n at recall@10 >= 0.99 (1 GPU)",
+            "workload": "prefixes of the sift-shaped synthetic 1,000,000 x 128 set, NSSG l = 100, "
+                        "R = 50, 60 degrees built on the GPU, 10,000 queries, K = 100", "rows": rows,
+            "data": "synthetic (seeded)"}
 
 
 def bench_sharded(a):
