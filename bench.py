@@ -82,12 +82,13 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build", "sharded", "alpha",
-                                                        "scaling"],
+                                                        "scaling", "exact"],
                     help="c2: the headline search; c3: storage precisions on 960-d data; "
                          "c4: mixed L/K batched form; c5: serving; build: GPU index build "
                          "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set; sharded: "
                          "partitioned search over random shards on the 1M x 128 set; alpha: "
-                         "minimum-angle sweep; scaling: build and search cost against n")
+                         "minimum-angle sweep; scaling: build and search cost against n; exact: "
+                         "exact SSG (Alg. 2) degrees and greedy path lengths on 10,000 points")
     ap.add_argument("--shards", type=int, default=4, help="sharded: number of shards")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
@@ -108,6 +109,9 @@ def main():
     import synth
     from paper_1907_06146_amd import graph_io, search
 
+    if a.workload == "exact":
+        print(json.dumps(bench_exact(a)), flush=True)
+        return
     if a.workload in ("alpha", "scaling"):
         print(json.dumps(bench_alpha(a) if a.workload == "alpha" else bench_scaling(a)), flush=True)
         return
@@ -420,6 +424,62 @@ def bench_batched(a):
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
     return out
+
+
+def bench_exact(a):
+    """Exact SSG study (the paper's table on SIFT10K, here on 10,000 points of
+    the SIFT-shaped synthetic mixture): Alg. 2 graphs for 60 and 30 degrees
+    built on the GPU, their average and maximum out-degree, and for graphs of
+    at most 64 out-edges per node (the search kernel's row width: the graphs
+    truncated at 40 and 64 edges) the greedy path length of Alg. 1 with L = 1
+    from a random start: for 1,000 indexed queries (base points; success =
+    the query itself is found) and 1,000 unindexed queries (success = the
+    exact nearest neighbour is found)."""
+    import torch
+
+    import synth
+    from paper_1907_06146_amd import search
+    from paper_1907_06146_amd.binding import exact_ssg
+
+    base = np.ascontiguousarray(synth.base_vectors("c2s")[:10_000])
+    n = len(base)
+    unq = synth.queries("c2s", synth.base_vectors("c2s"))[:1000]
+    rng = np.random.default_rng(2024)
+    idx_q = rng.choice(n, 1000, replace=False)
+    qs = np.concatenate([base[idx_q], unq]).astype(np.float32)
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tq = torch.from_numpy(qs).to(dev)
+    # exact nearest neighbour of each unindexed query (FP64, ties by id)
+    b64 = base.astype(np.float64)
+    nn = np.array([int(np.lexsort((np.arange(n), ((b64 - u) ** 2).sum(1)))[0]) for u in unq.astype(np.float64)])
+    starts = torch.from_numpy(rng.integers(0, n, (len(qs), 1)).astype(np.int32)).to(dev)
+    rows = []
+    for alpha in (60.0, 30.0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        full, deg = exact_ssg(tb, alpha, cap=64)
+        dt = time.perf_counter() - t0
+        deg = deg.cpu().numpy()
+        for cap in (40, 64):
+            g = full[:, :cap].contiguous()
+            ids, _, _, hops = search(tb, g, starts, tq, 1, 1, stats=True, entry_group_size=1)
+            torch.cuda.synchronize()
+            ids = ids.cpu().numpy()[:, 0]
+            hops = hops.cpu().numpy().astype(np.float64)
+            gk = (g >= 0).sum(1).cpu().numpy()
+            rows.append({"alpha": alpha, "build_s": dt, "aod_full": float(deg.mean()),
+                         "mod_full": int(deg.max()), "truncated_at": cap, "aod": float(gk.mean()),
+                         "mod": int(gk.max()),
+                         "path_indexed": float(hops[:1000].mean() - 1.0),
+                         "found_indexed": float((ids[:1000] == idx_q).mean()),
+                         "path_unindexed": float(hops[1000:].mean() - 1.0),
+                         "found_unindexed": float((ids[1000:] == nn).mean())})
+            log(f"exact SSG: {rows[-1]}")
+    return {"metric": "exact SSG degrees and greedy (L = 1) path lengths, 10,000 x 128, 1 GPU",
+            "workload": "10,000 points of the sift-shaped synthetic mixture; path length = moves "
+                        "of Alg. 1 with L = 1 from a random start (expansions - 1)", "rows": rows,
+            "data": "synthetic (seeded)"}
 
 
 def _gpu_nssg(tb, knn, cfg, alpha):

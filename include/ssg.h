@@ -297,6 +297,23 @@ int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t S, int64_t
                      const uint32_t* id_map, const int64_t* map_off, int32_t K_out,
                      uint32_t* out_ids, float* out_dists, void* stream);
 
+/*
+ * ssg_exact_ssg -- the exact satellite system graph (Alg. 2): for every node
+ * i, all other points in ascending (squared distance, id) order (distance 0
+ * dropped), each kept unless a kept edge makes an angle below alpha with it
+ * (the rule of ssg_nssg_prune, FP64), with no degree bound.
+ *   base       DEVICE float32 n x d, 2 <= n <= 2^20 (cost grows as n^2)
+ *   cos2a      cos^2 of the minimum angle
+ *   out        DEVICE uint32 n x cap: the first cap kept ids in selection
+ *              order (the graph truncated at cap), then padding
+ *   deg        DEVICE int32[n]: the untruncated out-degree
+ *   workspace  DEVICE, 256-byte aligned, ssg_exact_ssg_workspace_bytes(n)
+ * Asynchronous on stream.
+ */
+size_t ssg_exact_ssg_workspace_bytes(int64_t n);
+int ssg_exact_ssg(const float* base, int64_t n, int32_t d, double cos2a, int32_t cap, uint32_t* out,
+                  int32_t* deg, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);
 

@@ -27,7 +27,7 @@ EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
            "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
            "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse",
-           "ssg_merge_shards")
+           "ssg_merge_shards", "ssg_exact_ssg_workspace_bytes", "ssg_exact_ssg")
 
 
 class SSGError(RuntimeError):
@@ -114,6 +114,10 @@ def lib() -> ctypes.CDLL:
             L.ssg_nssg_reverse.restype = ctypes.c_int
             L.ssg_merge_shards.argtypes = [P, P, i32, i64, i32, P, P, i32, P, P, P]
             L.ssg_merge_shards.restype = ctypes.c_int
+            L.ssg_exact_ssg_workspace_bytes.argtypes = [i64]
+            L.ssg_exact_ssg_workspace_bytes.restype = sz
+            L.ssg_exact_ssg.argtypes = [P, i64, i32, dbl, i32, P, P, P, sz, P]
+            L.ssg_exact_ssg.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

@@ -193,3 +193,24 @@ def nssg_graph(base, knn_k: int, l: int, R: int, alpha: float = 60.0):
     ids, _, _ = knn_graph(base, knn_k)
     g1 = nssg_prune(base, ids, l, R, alpha)
     return nssg_reverse(base, g1, alpha), ids
+
+
+def exact_ssg(base, alpha: float = 60.0, cap: int | None = None, stream=None):
+    """Exact satellite system graph (Alg. 2) on the GPU. Returns (adjacency
+    int32 [n, cap] truncated at cap (default: n - 1, the whole graph), and
+    the untruncated out-degrees int32 [n]). Synchronous."""
+    _need_cuda("base", base, (torch.float32,))
+    n, d = base.shape
+    cap = cap or (n - 1)
+    st = stream if stream is not None else torch.cuda.current_stream(base.device)
+    L = _lib.lib()
+    nbytes = L.ssg_exact_ssg_workspace_bytes(n)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=base.device)
+    off = (-ws.data_ptr()) % 256
+    out = torch.empty((n, cap), dtype=torch.int32, device=base.device)
+    deg = torch.empty(n, dtype=torch.int32, device=base.device)
+    rc = L.ssg_exact_ssg(_ptr(base), n, d, cos2(alpha), cap, _ptr(out), _ptr(deg),
+                         ctypes.c_void_p(ws.data_ptr() + off), nbytes, ctypes.c_void_p(st.cuda_stream))
+    _lib.check(rc)
+    st.synchronize()
+    return out, deg

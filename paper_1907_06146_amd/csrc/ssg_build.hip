@@ -311,6 +311,90 @@ __global__ __launch_bounds__(64) void reverse_kernel(ReverseArgs a) {
   for (int t = lane; t < a.R; t += 64) a.out[j * a.R + t] = t < kept ? kid[t] : kSent;
 }
 
+// ------------------------------------------------------------- exact SSG
+// Alg. 2 over all pairs: node i's candidates are all other points in
+// ascending (distance, id) order (distance 0 dropped), selected by the rule
+// of wave_select without a degree bound. One wavefront per node; the
+// candidates are sorted by a bitonic network in a workspace slice, and lane k
+// tests a candidate against kept edges k, k + 64, ...
+struct ExactArgs {
+  const float* base;
+  int64_t n;
+  int d;
+  double cos2a;
+  int cap;
+  int64_t first;       // first node of this launch
+  int64_t npad;        // sort length (power of two >= n)
+  Cand* scratch;       // [nodes per launch][npad]
+  uint32_t* kept_id;   // [nodes per launch][n]
+  double* kept_len;    // [nodes per launch][n]
+  uint32_t* out;       // n x cap
+  int32_t* deg;        // n
+};
+
+__global__ __launch_bounds__(64) void exact_ssg_kernel(ExactArgs a) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  const int64_t slot = blockIdx.x;
+  const int64_t i = a.first + slot;
+  if (i >= a.n) return;
+  Cand* c = a.scratch + slot * a.npad;
+  uint32_t* kid = a.kept_id + slot * a.n;
+  double* klen = a.kept_len + slot * a.n;
+  const float* xi = a.base + i * a.d;
+  for (int64_t j = lane; j < a.npad; j += 64) {
+    Cand v;
+    v.id = (uint32_t)j;
+    v.pad = 0;
+    v.dist = INFINITY;  // padding, itself and distance 0 sort last and are cut
+    if (j < a.n && j != i) {
+      const double dd = ssgdev::exact_l2(xi, a.base + j * a.d, a.d);
+      if (dd != 0.0) v.dist = dd;
+    }
+    if (j >= a.n) v.id = kSent;
+    c[j] = v;
+  }
+  __syncthreads();  // one wavefront per block; orders its global scratch accesses
+  // bitonic sort of npad entries by (dist, id)
+  for (int64_t k = 2; k <= a.npad; k <<= 1) {
+    for (int64_t jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int64_t t = lane; t < a.npad; t += 64) {
+        const int64_t u = t ^ jj;
+        if (u > t) {
+          const Cand x = c[t], y = c[u];
+          const bool up = (t & k) == 0;
+          if (up ? cand_less(y, x) : cand_less(x, y)) {
+            c[t] = y;
+            c[u] = x;
+          }
+        }
+      }
+      __syncthreads();  // one wavefront per block; orders its global scratch accesses
+    }
+  }
+  int kept = 0;
+  for (int64_t cc = 0; cc < a.n; ++cc) {
+    const Cand cd = c[cc];
+    if (cd.dist == INFINITY) break;
+    const float* xc = a.base + (int64_t)cd.id * a.d;
+    bool conflict = false;
+    for (int k = lane; k < kept && !conflict; k += 64) {
+      const double dot = ssgdev::dot_rel(xc, a.base + (int64_t)kid[k] * a.d, xi, a.d);
+      conflict = dot > 0.0 && dot * dot > a.cos2a * cd.dist * klen[k];
+    }
+    if (__ballot(conflict) == 0) {
+      if (lane == 0) {
+        kid[kept] = cd.id;
+        klen[kept] = cd.dist;
+      }
+      ++kept;
+      __syncthreads();  // one wavefront per block; orders its global scratch accesses
+    }
+  }
+  for (int t = lane; t < a.cap; t += 64) a.out[i * a.cap + t] = t < kept ? kid[t] : kSent;
+  if (lane == 0) a.deg[i] = kept;
+}
+
 int fail_msg(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail_msg(int code, const char* fmt, ...) {
   char buf[512];
@@ -322,6 +406,14 @@ int fail_msg(int code, const char* fmt, ...) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int64_t EXACT_CHUNK = 1024;  // nodes per exact-SSG launch
+
+int64_t pow2_at_least(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
 
 struct RevLayout {
   size_t cnt, fill, off, bsum, rev, scratch, total;
@@ -345,6 +437,51 @@ RevLayout rev_layout(int64_t n, int R) {
 }  // namespace
 
 extern "C" {
+
+size_t ssg_exact_ssg_workspace_bytes(int64_t n) {
+  if (n < 2) return 0;
+  const int64_t npad = pow2_at_least(n);
+  return align256((size_t)EXACT_CHUNK * npad * sizeof(Cand)) + align256((size_t)EXACT_CHUNK * n * 4) +
+         align256((size_t)EXACT_CHUNK * n * 8);
+}
+
+int ssg_exact_ssg(const float* base, int64_t n, int32_t d, double cos2a, int32_t cap, uint32_t* out,
+                  int32_t* deg, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!base || !out || !deg || !workspace) return fail_msg(SSG_EINVAL, "ssg_exact_ssg: null pointer argument");
+  if (n < 2 || n > (1 << 20) || d < 1 || cap < 1)
+    return fail_msg(SSG_EINVAL, "ssg_exact_ssg: n=%lld d=%d cap=%d out of range (n <= 2^20)", (long long)n, d, cap);
+  if (!(cos2a >= 0.0 && cos2a <= 1.0)) return fail_msg(SSG_EINVAL, "ssg_exact_ssg: cos2a outside [0, 1]");
+  const size_t need = ssg_exact_ssg_workspace_bytes(n);
+  if (workspace_bytes < need)
+    return fail_msg(SSG_EINVAL, "ssg_exact_ssg: workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail_msg(SSG_EINVAL, "ssg_exact_ssg: workspace not 256-byte aligned");
+  const int64_t npad = pow2_at_least(n);
+  char* w = static_cast<char*>(workspace);
+  ExactArgs a{};
+  a.base = base;
+  a.n = n;
+  a.d = d;
+  a.cos2a = cos2a;
+  a.cap = cap;
+  a.npad = npad;
+  a.scratch = reinterpret_cast<Cand*>(w);
+  a.kept_id = reinterpret_cast<uint32_t*>(w + align256((size_t)EXACT_CHUNK * npad * sizeof(Cand)));
+  a.kept_len = reinterpret_cast<double*>(w + align256((size_t)EXACT_CHUNK * npad * sizeof(Cand)) +
+                                         align256((size_t)EXACT_CHUNK * n * 4));
+  a.out = out;
+  a.deg = deg;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int64_t f = 0; f < n; f += EXACT_CHUNK) {
+    a.first = f;
+    const int64_t m = n - f < EXACT_CHUNK ? n - f : EXACT_CHUNK;
+    hipLaunchKernelGGL(exact_ssg_kernel, dim3((unsigned)m), dim3(64), 0, s, a);
+  }
+  if (hipGetLastError() != hipSuccess)
+    return fail_msg(SSG_EDEVICE, "ssg_exact_ssg: launch failed: %s", hipGetErrorString(hipGetLastError()));
+  ssg_internal_clear_error();
+  return SSG_OK;
+}
 
 int ssg_nssg_prune(const float* base, int64_t n, int32_t d, const uint32_t* knn, int32_t Kk,
                    int32_t l, int32_t R, double cos2a, uint32_t* out, void* stream) {

@@ -93,3 +93,26 @@ def test_full_size_sift_shaped_graph():
         k = int(np.nonzero(row == u)[0][0])
         og[w] = np.concatenate([np.delete(row, k), [SENT]]).astype(np.uint32)
     assert np.array_equal(g2, og), f"{(g2 != og).any(1).sum()} rows differ"
+
+
+@pytest.mark.parametrize("alpha", [60.0, 30.0])
+def test_exact_ssg_float_points(alpha):
+    """Alg. 2 over all pairs, points in general position: identical adjacency
+    lists (in selection order) and degrees."""
+    from paper_1907_06146_amd.binding import exact_ssg
+    base = np.random.default_rng(9).standard_normal((1500, 8)).astype(np.float32)
+    gi, gd = exact_ssg(_dev(base), alpha)
+    oi, od = core.ssg_exact(base, alpha)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert np.array_equal(_host(gi), oi)
+
+
+def test_exact_ssg_integer_data_truncated():
+    """SIFT-like integer vectors (duplicates dropped at distance 0), truncated
+    at 16 edges: the first 16 of the full selection, full degrees."""
+    from paper_1907_06146_amd.binding import exact_ssg
+    base = synth.base_vectors("c2s")[:2000]
+    gi, gd = exact_ssg(_dev(base), 60.0, cap=16)
+    oi, od = core.ssg_exact(base, 60.0)
+    assert np.array_equal(gd.cpu().numpy(), od)
+    assert np.array_equal(_host(gi), oi[:, :16])
