@@ -43,6 +43,7 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <type_traits>
 
 #include "ssg.h"
 #include "ssg_internal.h"
@@ -312,35 +313,48 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
           const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)idp[p] * a.dc * 16);
 #pragma unroll
           for (int t = 0; t < NCH; ++t) {
+            // lanes past the batch read row 0 (idp = 0) and their sums are
+            // discarded; loading unconditionally avoids zeroing the registers
             const int ch = g + G * t;
-            if (vp[p] && (DC % G == 0 || ch < DC)) buf[p][t] = vec[ch];
+            if (DC % G == 0 || ch < DC) buf[p][t] = vec[ch];
             else buf[p][t] = make_uint4(0, 0, 0, 0);
           }
         }
+        // the metric is uniform: branch once per pass, not per element
+        auto accumulate = [&](auto ip_c) {
+          constexpr bool IP = decltype(ip_c)::value;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
+          for (int p = 0; p < NP; ++p) {
 #pragma unroll
-          for (int t = 0; t < NCH; ++t) {
-            const int ch = g + G * t;
-            if (DC % G == 0 || ch < DC) {
-              float x[EPC];
-              T::decode(buf[p][t], x);
+            for (int t = 0; t < NCH; ++t) {
+              const int ch = g + G * t;
+              if (DC % G == 0 || ch < DC) {
+                float x[EPC];
+                T::decode(buf[p][t], x);
 #pragma unroll
-              for (int e = 0; e < EPC; ++e) {
-                float sv, qv;
-                if constexpr (kQueryInRegs) {
-                  sv = kScaled ? sf[t * EPC + e] : 1.f;
-                  qv = qf[t * EPC + e];
-                } else {
-                  sv = kScaled ? qlds[a.d + ch * EPC + e] : 1.f;
-                  qv = qlds[ch * EPC + e];
+                for (int e = 0; e < EPC; ++e) {
+                  float sv, qv;
+                  if constexpr (kQueryInRegs) {
+                    sv = kScaled ? sf[t * EPC + e] : 1.f;
+                    qv = qf[t * EPC + e];
+                  } else {
+                    sv = kScaled ? qlds[a.d + ch * EPC + e] : 1.f;
+                    qv = qlds[ch * EPC + e];
+                  }
+                  const float xv = kScaled ? __fmul_rn(x[e], sv) : x[e];
+                  if constexpr (IP) {
+                    acc[p] = fmaf(qv, xv, acc[p]);
+                  } else {
+                    const float df = qv - xv;
+                    acc[p] = fmaf(df, df, acc[p]);
+                  }
                 }
-                const float xv = kScaled ? __fmul_rn(x[e], sv) : x[e];
-                acc[p] = term(acc[p], qv, xv);
               }
             }
           }
-        }
+        };
+        if (ip) accumulate(std::true_type{});
+        else accumulate(std::false_type{});
       } else {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
