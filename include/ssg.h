@@ -62,7 +62,7 @@ typedef struct {
     int32_t exact_visited;    /* 1: visited set is an exact n-bit LDS bitset
                                  (requires n <= SSG_EXACT_VISITED_MAX_N); the
                                  distance count then equals Alg. 1's exactly */
-    int32_t hash_log2;        /* log2 of the LDS visited-hash size; 0 = default */
+    int32_t hash_log2;        /* log2 of the LDS visited-set entry count; 0 = default */
     int32_t waves_per_block;  /* wavefronts (queries) per workgroup; 0 = default */
     int32_t* out_ndc;         /* DEVICE int32[nq] distance computations, or NULL */
     int32_t* out_hops;        /* DEVICE int32[nq] expansions, or NULL */
@@ -80,6 +80,14 @@ typedef struct {
                                  several shards' graphs, stored as one
                                  block-diagonal graph, in one launch;
                                  0 = every query uses the same n_entry ids */
+    int32_t visited_kind;     /* form of the visited set when exact_visited is 0:
+                                 0 = default (the tag cache when a 16-bit tag
+                                 holds the ids, else the hash); 1 = hash of full
+                                 ids, cleared and refilled from the pool when
+                                 half full; 2 = 4-way tag cache (SSG_EUNSUPPORTED
+                                 when the ids do not fit). Either form may forget
+                                 ids, which costs recomputed distances but never
+                                 changes the results. */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144

@@ -41,7 +41,7 @@ class SearchOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
                 ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
                 ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32),
-                ("entry_group_size", ctypes.c_int64)]
+                ("entry_group_size", ctypes.c_int64), ("visited_kind", ctypes.c_int32)]
 
 
 class BatchDesc(ctypes.Structure):

@@ -30,10 +30,14 @@ def _need_cuda(name, t, dtypes=None):
         raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
 
 
+_VISITED = {"auto": 0, "hash": 1, "cache": 2}
+
+
 def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
            waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0,
-           base_f32=None, rerank_k: int = 0, out=None, stream=None, entry_group_size: int = 0):
+           base_f32=None, rerank_k: int = 0, out=None, stream=None, entry_group_size: int = 0,
+           visited: str = "auto"):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -47,6 +51,8 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     entry_group_size  > 0: entry_ids is [G, s] and queries g*size .. (g+1)*size-1
                start from row g (several shards stored as one block-diagonal
                graph, searched in one launch).
+    visited    "auto" | "hash" | "cache": form of the LDS visited set (ignored
+               with exact_visited); every form gives the same results.
     """
     _need_cuda("base", base, tuple(_DTYPES))
     _need_cuda("graph", graph, (torch.int32, torch.uint32))
@@ -86,7 +92,7 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
                            None if ndc is None else ndc.data_ptr(),
                            None if hops is None else hops.data_ptr(), gather_variant,
                            None if base_f32 is None else base_f32.data_ptr(), rerank_k,
-                           entry_group_size)
+                           entry_group_size, _VISITED[visited])
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,

@@ -12,12 +12,21 @@
 //             An entry is one 64-bit key  ord(dist) << 32 | id << 1 | checked,
 //             so unsigned order is the (dist, id) order and the checked flag
 //             never decides it (ids in the pool are distinct).
-//   visited   LDS open-addressing hash of node ids that always contains every
-//             id in the pool. When it is half full it is cleared and refilled
-//             from the pool. Forgetting a node that has left the pool cannot
-//             change the result: it left because its key exceeded the L-th
-//             key, which never grows afterwards, so a recomputed copy is cut
-//             again at once. Optional exact mode: an n-bit LDS bitset.
+//   visited   which node ids already have a distance. Forgetting an id can
+//             only cost a recomputation, never change the result: a node that
+//             left the pool left because its key exceeded the L-th key, which
+//             never grows afterwards, so a recomputed copy is cut again at
+//             once; a node still in the pool comes back with the same key and
+//             is dropped before the merge. Three forms, all in LDS:
+//               cache  (default) 4-way set-associative, 16-bit entries. The
+//                      id is mapped by a bijection of its low k bits
+//                      (multiplication by an odd constant mod 2^k); the high
+//                      bits pick the set and the rest is the stored tag, so a
+//                      hit is never false. A full set overwrites one way.
+//               hash   open addressing of full ids, cleared and refilled from
+//                      the pool when half full (used when the tag would not
+//                      fit 16 bits).
+//               exact  an n-bit bitset.
 //   stage     LDS scratch for the merge (L keys), batch ids and keys (64 each).
 //
 // One iteration (one expansion of Alg. 1):
@@ -85,6 +94,39 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
   uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
   return ((uint64_t)hi << 32) | lo;
 }
+// x + the value of lane ^ OFF. Within a row of 16 lanes the partner comes
+// from a DPP lane move (VALU; row_shr:n reads lane i - n, row_shl:n lane
+// i + n, quad_perm permutes each quad), across rows from a lane shuffle.
+// Call with every lane active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int OFF>
+__device__ __forceinline__ float add_xor_lane(float x, int lane) {
+  if constexpr (OFF == 1) return x + dpp_f32<0xB1>(x);  // quad_perm [1,0,3,2]
+  if constexpr (OFF == 2) return x + dpp_f32<0x4E>(x);  // quad_perm [2,3,0,1]
+  if constexpr (OFF == 4 || OFF == 8) {
+    const float lo = dpp_f32<0x110 + OFF>(x);  // row_shr: lane - OFF
+    const float hi = dpp_f32<0x100 + OFF>(x);  // row_shl: lane + OFF
+    return x + ((lane & OFF) ? lo : hi);
+  }
+  if constexpr (OFF >= 16) return x + __shfl_xor(x, OFF, 64);
+}
+// Sum over each aligned group of G lanes, on every lane of the group; the
+// same additions in the same order as a butterfly of lane shuffles from
+// offset G/2 down to 1.
+template <int G>
+__device__ __forceinline__ float group_sum(float x, int lane) {
+  if constexpr (G >= 64) x = add_xor_lane<32>(x, lane);
+  if constexpr (G >= 32) x = add_xor_lane<16>(x, lane);
+  if constexpr (G >= 16) x = add_xor_lane<8>(x, lane);
+  if constexpr (G >= 8) x = add_xor_lane<4>(x, lane);
+  if constexpr (G >= 4) x = add_xor_lane<2>(x, lane);
+  if constexpr (G >= 2) x = add_xor_lane<1>(x, lane);
+  return x;
+}
+
 // Minimum of a 64-bit value over the wavefront, read back on every lane.
 // Row-local DPP shifts (VALU latency, not the LDS pipe of lane shuffles)
 // reduce each row of 16 into its lane 15; row broadcasts fold the four rows
@@ -197,8 +239,9 @@ struct Args {
   float* out_d;
   int32_t* out_ndc;
   int32_t* out_hops;
-  int32_t exact;       // 1: bitset visited
-  int32_t hash_log2;   // hash mode: log2 table size
+  int32_t vmode;       // visited form: 0 exact bitset, 1 hash, 2 tag cache
+  int32_t hash_log2;   // hash / cache: log2 of the number of entries
+  int32_t id_bits;     // cache: k, with every id < 2^k (k - (hash_log2 - 2) <= 15)
   int32_t lds_per_wave;
   const float* base_f32;  // FP32 vectors for the final rerank, or null
   int32_t rerank;         // pool entries to rerank (<= 64 * PREG); -1: K of each query
@@ -275,9 +318,13 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
 
   // visited structure
   const uint32_t hmask = (1u << a.hash_log2) - 1u;
-  const int twords = a.exact ? (int)((a.n + 31) >> 5) : (int)(hmask + 1u);
-  const uint32_t tfill = a.exact ? 0u : kSent;
+  const int twords = a.vmode == 0 ? (int)((a.n + 31) >> 5)
+                     : a.vmode == 2 ? (int)((hmask + 1u) >> 1)
+                                    : (int)(hmask + 1u);
+  const uint32_t tfill = a.vmode == 1 ? kSent : 0u;
   for (int i = lane; i < twords; i += 64) table[i] = tfill;
+  const int tshift = a.id_bits - (a.hash_log2 - 2);           // cache: tag bits
+  const uint32_t kmask = (uint32_t)((1ull << a.id_bits) - 1u);
   wave_sync();
   int hcount = 0;                         // ids inserted since the last clear
   const int hlimit = (int)((hmask + 1u) >> 1);
@@ -375,8 +422,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       }
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-#pragma unroll
-        for (int off = G / 2; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, 64);
+        acc[p] = group_sum<G>(acc[p], lane);
         if (vp[p] && g == 0) bkeys[c0 + p * CPP + grp] = make_key(ip ? -acc[p] : acc[p], idp[p]);
       }
     }
@@ -385,7 +431,23 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
 
   // test-and-insert id; returns true when the id was not yet visited
   auto visit = [&](uint32_t id) -> bool {
-    if (a.exact) {
+    if (a.vmode == 2) {
+      // set = high bits of the k-bit image, tag = the rest + 1 (0 marks empty)
+      const uint32_t h = (id * 0x9E3779B1u) & kmask;
+      const uint32_t set = h >> tshift;
+      const uint32_t tag = (h & ((1u << tshift) - 1u)) + 1u;
+      const uint64_t w = reinterpret_cast<const uint64_t*>(table)[set];
+      const uint32_t t0 = (uint32_t)w & 0xFFFFu, t1 = (uint32_t)(w >> 16) & 0xFFFFu;
+      const uint32_t t2 = (uint32_t)(w >> 32) & 0xFFFFu, t3 = (uint32_t)(w >> 48);
+      if (t0 == tag || t1 == tag || t2 == tag || t3 == tag) return false;
+      // lanes that pick the same way in one step overwrite each other: a loss
+      // is a forgotten id, which is allowed
+      const uint32_t way = t0 == 0u ? 0u : t1 == 0u ? 1u : t2 == 0u ? 2u : t3 == 0u ? 3u
+                                                                               : (tag ^ (tag >> 2)) & 3u;
+      reinterpret_cast<uint16_t*>(table)[set * 4u + way] = (uint16_t)tag;
+      return true;
+    }
+    if (a.vmode == 0) {
       const uint32_t bit = 1u << (id & 31u);
       const uint32_t old = atomicOr(&table[id >> 5], bit);
       return (old & bit) == 0u;
@@ -435,7 +497,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     if (hops > a.n + 1) break;  // cannot happen (each node is expanded at most once); bounds the loop
 
     // visited table maintenance: rebuild from the pool when half full
-    if (!a.exact && hcount + R > hlimit) {
+    if (a.vmode == 1 && hcount + R > hlimit) {
       for (int i = lane; i <= (int)hmask; i += 64) table[i] = kSent;
       wave_sync();
 #pragma unroll
@@ -479,17 +541,38 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
           if (k == ((L - 1) >> 6)) worst = readlane64(pool[k], (L - 1) & 63);
         if (b > worst) b = kNoKey;
       }
+      if (a.vmode == 2) {
+        // a pool member the cache forgot comes back with its pool key (up to
+        // the checked bit); drop it so the pool never holds an id twice
+        // (an id decides it: equal ids have equal keys; the low word of a key
+        // is id << 1 | checked, and ids stay below 2^31 - 1)
+        uint32_t plo[PREG];
+#pragma unroll
+        for (int k = 0; k < PREG; ++k) plo[k] = (uint32_t)pool[k] | 1u;
+        for (uint64_t mm = __ballot(b != kNoKey); mm; mm &= mm - 1) {
+          const int j = __builtin_ctzll(mm);
+          const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j) | 1u;
+          uint64_t hit = 0;
+#pragma unroll
+          for (int k = 0; k < PREG; ++k) hit |= __ballot(plo[k] == bj);
+          if (hit && lane == j) b = kNoKey;
+        }
+      }
     }
     const uint64_t bm = __ballot(b != kNoKey);  // new keys that can enter the pool
 
     // next expansion, decided before the merge so its row read overlaps it:
     // the smallest unchecked key u of (pool + new keys) is kept iff fewer
-    // than L keys precede it; otherwise every kept entry is checked.
-    u = min(u, wave_min64(b));
-    int rank_u = __popcll(__ballot(b < u));
+    // than L keys precede it; otherwise every kept entry is checked. When no
+    // new key is below u_spec, u_spec keeps its pool position (< L).
+    bool more = u != kNoKey;
+    if (__ballot(b < u)) {
+      u = wave_min64(b);  // below u_spec, so the smallest unchecked key
+      int rank_u = 0;     // (no new key is below u)
 #pragma unroll
-    for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
-    const bool more = u != kNoKey && rank_u < L;
+      for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
+      more = rank_u < L;
+    }
     uint32_t nb_next = nb_spec;
     if (more && u != u_spec) nb_next = lane < R ? a.graph[(size_t)key_id(u) * R + lane] : kSent;
 
@@ -518,7 +601,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       }
       if (b != kNoKey && rank + qcnt < L) stage[rank + qcnt] = b;
       wave_sync();
-      size = min(L, size + __popcll(bm));
+      size = min(L, size + (int)__popcll(bm));
 #pragma unroll
       for (int k = 0; k < PREG; ++k) {
         const int i = k * 64 + lane;
@@ -565,8 +648,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
             acc = term(acc, qq.w, x.w);
           }
         }
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        acc = group_sum<16>(acc, lane);
         if (c < cm && l16 == 0) rkeys[c0 + c] = make_key(ip ? -acc : acc, id);
       }
       wave_sync();
@@ -902,31 +984,51 @@ Launch pick_launch(int dtype, int dc, int preg, int variant, bool batched) {
                              : Table<FP8T>::pick(dc, preg, variant, batched);
 }
 
-// LDS bytes per wavefront and the hash size for a pool capacity of 64*preg.
-int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, bool exact, int64_t n,
-               bool rerank, int hash_log2_req, int* hash_log2_out, size_t* per_wave) {
+// LDS bytes per wavefront and the visited form for a pool capacity of 64*preg.
+// kind: 0 = the tag cache where a 16-bit tag holds the ids, else the hash;
+// 1 = hash; 2 = cache (fails when the ids do not fit); 3 = exact bitset.
+struct VisitedPlan {
+  int vmode = 1, hash_log2 = 0, id_bits = 0;
+  size_t per_wave = 0;
+};
+int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, int kind, int64_t n,
+               bool rerank, int hash_log2_req, VisitedPlan* vp) {
   const int lcap = 64 * preg;
   size_t fixed = (size_t)lcap * 8 + 64 * 8 + 64 * 4 +
                  (query_in_regs ? 0 : (size_t)d * 4 * (dtype == SSG_FP8E4M3 ? 2 : 1));
   size_t table;
-  if (exact) {
+  if (kind < 0 || kind > 3) return fail(SSG_EINVAL, "visited_kind must be in [0, 3]");
+  if (kind == 3) {
     if (n > SSG_EXACT_VISITED_MAX_N)
       return fail(SSG_EUNSUPPORTED, "exact visited set needs n <= %d", SSG_EXACT_VISITED_MAX_N);
     table = (size_t)((n + 31) / 32) * 4;
-    if (rerank) table = std::max(table, (size_t)lcap * 8);
-    *hash_log2_out = 0;
+    vp->vmode = 0;
+    vp->hash_log2 = 0;
   } else {
-    // default table: 2048 ids for FP32 vectors, 1024 for BF16 / FP8, whose
-    // cheaper recomputation favours the smaller LDS footprint (measured on the
-    // 1M x 128 workload)
-    int hl = hash_log2_req > 0 ? hash_log2_req : (dtype == SSG_F32 ? 11 : 10);
-    // the table must hold the pool plus one row at load <= 1/2
-    while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
-    if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");
-    *hash_log2_out = hl;
-    table = (size_t)4 << hl;
+    // default size: 4096 entries (8 KB as a tag cache), fastest for FP32,
+    // BF16 and FP8 vectors on the 1M x 128 workload
+    int hl = hash_log2_req > 0 ? hash_log2_req : 12;
+    if (hl < 4 || hl > 15) return fail(SSG_EINVAL, "hash_log2 must be in [4, 15]");
+    int k = 0;
+    while (k < 32 && ((uint64_t)1 << k) < (uint64_t)n) ++k;  // every id < 2^k
+    k = std::max(k, hl - 2);
+    const bool fits = k - (hl - 2) <= 15;
+    if (kind == 2 && !fits)
+      return fail(SSG_EUNSUPPORTED, "visited cache: ids of n = %lld need tags over 16 bits at hash_log2 %d",
+                  (long long)n, hl);
+    vp->vmode = kind == 1 || !fits ? 1 : 2;
+    if (vp->vmode == 1) {
+      // the hash must hold the pool plus one row at load <= 1/2; the cache has
+      // no such need (a small one forgets more and recomputes more)
+      while ((1 << hl) < 2 * (lcap + R) + 64) ++hl;
+      if (hl > 15) return fail(SSG_EINVAL, "hash_log2 too large");
+    }
+    vp->hash_log2 = hl;
+    vp->id_bits = vp->vmode == 2 ? k : 0;
+    table = vp->vmode == 2 ? (size_t)2 << hl : (size_t)4 << hl;
   }
-  *per_wave = (fixed + table + 15) & ~(size_t)15;
+  if (rerank) table = std::max(table, (size_t)lcap * 8);  // the rerank reuses it for keys
+  vp->per_wave = (fixed + table + 15) & ~(size_t)15;
   return SSG_OK;
 }
 
@@ -1010,7 +1112,6 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.counter = nullptr;
   if (o.entry_group_size < 0) return fail(SSG_EINVAL, "entry_group_size must be >= 0");
   a.entry_group = o.entry_group_size;
-  a.exact = o.exact_visited ? 1 : 0;
   a.base_f32 = o.base_f32;
   a.rerank = 0;
   if (o.base_f32) {
@@ -1019,10 +1120,14 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
     if (o.rerank_k < 0) return fail(SSG_EINVAL, "rerank_k must be >= 0");
     a.rerank = std::min(o.rerank_k > 0 ? o.rerank_k : K, L);
   }
-  size_t per_wave = 0;
-  rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, a.exact != 0, n, o.base_f32 != nullptr,
-                  o.hash_log2, &a.hash_log2, &per_wave);
+  VisitedPlan vp;
+  rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, o.exact_visited ? 3 : o.visited_kind, n,
+                  o.base_f32 != nullptr, o.hash_log2, &vp);
   if (rc) return rc;
+  a.vmode = vp.vmode;
+  a.hash_log2 = vp.hash_log2;
+  a.id_bits = vp.id_bits;
+  size_t per_wave = vp.per_wave;
   if (per_wave * wpb > 64 * 1024) {
     wpb = (int)((64 * 1024) / per_wave);
     if (wpb < 1) return fail(SSG_EUNSUPPORTED, "per-query LDS need %zu exceeds the CU", per_wave);
@@ -1137,10 +1242,14 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     Launch lc = pick_launch(D->dtype, dc, preg, b.gather_variant, true);
     BucketLaunch bl{};
     Args& a = bl.a;
-    size_t per_wave = 0;
-    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, false, D->n, D->base_f32 != nullptr,
-                    b.hash_log2, &a.hash_log2, &per_wave);
+    VisitedPlan vp;
+    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, 0, D->n, D->base_f32 != nullptr,
+                    b.hash_log2, &vp);
     if (rc) return rc;
+    a.vmode = vp.vmode;
+    a.hash_log2 = vp.hash_log2;
+    a.id_bits = vp.id_bits;
+    const size_t per_wave = vp.per_wave;
     int wpb = b.waves_per_block > 0 ? b.waves_per_block : 1;
     while (wpb > 1 && per_wave * wpb > 64 * 1024) --wpb;
     if (per_wave > 64 * 1024) return fail(SSG_EUNSUPPORTED, "bucket %d: LDS need too large", i);
@@ -1162,7 +1271,6 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     a.out_d = D->out_dists;
     a.out_ndc = D->out_ndc;
     a.out_hops = D->out_hops;
-    a.exact = 0;
     a.lds_per_wave = (int)per_wave;
     a.base_f32 = D->rerank != 0 ? D->base_f32 : nullptr;
     a.rerank = D->rerank;
@@ -1239,27 +1347,29 @@ int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
   for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipEventRecord(fork, cap);
+    // record every step; the first failure is reported after the capture ends
+    hipError_t ce = hipEventRecord(fork, cap);
     for (int i = 0; i < nb; ++i) {
-      hipStreamWaitEvent(br[i], fork, 0);
-      if (desc->nq > 0) enqueue_bucket(bl[i], br[i]);
-      hipEventRecord(join[i], br[i]);
-      hipStreamWaitEvent(cap, join[i], 0);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(br[i], fork, 0);
+      if (ce == hipSuccess && desc->nq > 0) enqueue_bucket(bl[i], br[i]);
+      if (ce == hipSuccess) ce = hipEventRecord(join[i], br[i]);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(cap, join[i], 0);
     }
-    hipError_t le = hipGetLastError();
+    const hipError_t le = hipGetLastError();
     e = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess && ce != hipSuccess) e = ce;
     if (e == hipSuccess && le != hipSuccess) e = le;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   for (int i = 0; i < nb; ++i) {
-    if (join[i]) hipEventDestroy(join[i]);
-    if (br[i]) hipStreamDestroy(br[i]);
+    if (join[i]) (void)hipEventDestroy(join[i]);
+    if (br[i]) (void)hipStreamDestroy(br[i]);
   }
-  if (fork) hipEventDestroy(fork);
-  if (cap) hipStreamDestroy(cap);
+  if (fork) (void)hipEventDestroy(fork);
+  if (cap) (void)hipStreamDestroy(cap);
   if (e != hipSuccess) {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     return fail(SSG_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   }
   auto* g = new (std::nothrow) ssg_batch_graph;

@@ -74,12 +74,15 @@ def c2s():
 def test_integer_data_bit_exact(c2s, L, K):
     base, q, g, entry = c2s
     oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
-    for exact in (True, False):
-        gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=exact)
-        assert np.array_equal(gi, oi)
-        assert np.array_equal(gd.astype(np.float64), od)
-        assert np.array_equal(ghops, ohops)
-        if exact:
+    for form in ("exact", "hash", "cache"):
+        if form == "exact":
+            gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=True)
+        else:
+            gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, visited=form)
+        assert np.array_equal(gi, oi), form
+        assert np.array_equal(gd.astype(np.float64), od), form
+        assert np.array_equal(ghops, ohops), form
+        if form == "exact":
             assert np.array_equal(gndc, ondc)
         else:
             assert (gndc >= ondc).all()
@@ -89,9 +92,25 @@ def test_hash_rebuilds_are_result_neutral(c2s):
     base, q, g, entry = c2s
     K, L = 100, 256
     oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
-    gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, hash_log2=10)  # smallest table
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, hash_log2=10, visited="hash")  # smallest
     assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od)
+    assert np.array_equal(ghops, ohops)
     assert (gndc > ondc).any()  # the table was rebuilt and nodes were recomputed
+
+
+@pytest.mark.parametrize("hash_log2,L", [(4, 64), (5, 256), (8, 512), (10, 100)])
+def test_forgetful_cache_is_result_neutral(c2s, hash_log2, L):
+    """A tag cache far smaller than the visited set forgets pool members too;
+    each comes back with its pool key and must be dropped, never doubled."""
+    base, q, g, entry = c2s
+    K = 50
+    oi, od, ondc, ohops = core.search(base, g, entry, q, K, L)
+    gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, hash_log2=hash_log2, visited="cache")
+    assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od)
+    assert np.array_equal(ghops, ohops)
+    assert (gndc >= ondc).all()
+    if hash_log2 <= 8:
+        assert (gndc > ondc).mean() > 0.5  # most queries recomputed something
 
 
 def test_bf16_storage_is_lossless_on_integer_data(c2s):
