@@ -54,6 +54,8 @@ def lib():
             L.orc_nssg_reverse.argtypes = [P, i64, i32, P, i32, f64, P]
             L.orc_dfs_connect.argtypes = [P, i64, i32, P, i32, P, i32, i32, P, i64]
             L.orc_dfs_connect.restype = i64
+            L.orc_threads.argtypes = [i32]
+            L.orc_threads.restype = i32
             L.orc_search.argtypes = [P, i64, i32, P, i32, P, i32, P, i64, i32, i32, P, P, i32,
                                      i32, P, P, P, P]
             L.orc_ssg_exact.argtypes = [P, i64, i32, f64, i32, P, P]
@@ -348,6 +350,11 @@ def nssg_build(base, knn, l: int, R: int, alpha: float, entry_ids, expand: str =
 
 
 # ------------------------------------------------------------------ Alg. 1
+def threads(n: int = 0) -> int:
+    """Set the oracle's thread count (n >= 1) and return the count in use."""
+    return int(lib().orc_threads(int(n)))
+
+
 def search(base, graph, entry_ids, Q, K: int, L: int, metric: str = "l2", forget: bool = False,
            seed_all: bool = False, L_arr=None, K_arr=None):
     """Alg. 1 (Search-on-Graph) from the navigating node nearest each query.

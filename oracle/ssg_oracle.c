@@ -446,6 +446,13 @@ static uint32_t nearest_entry(const float *base, int d, const uint32_t *entry, i
     return bid;
 }
 
+/* Thread count of the parallel loops (n < 1: leave it unchanged); returns
+ * the count that later parallel regions use. Timing only. */
+int orc_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
 /* Batched Alg. 1 over nq queries. Each query starts from its nearest
  * navigating node (flags bit 1: seed every navigating node instead).
  * flags bit 0: "forget" visited mode. Per-query L_arr/K_arr override L/K when

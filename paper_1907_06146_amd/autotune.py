@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the batched search.
 
 For every L bucket it times candidate shapes -- gather variant (lanes per
-candidate and loads in flight), visited-hash size, wavefronts per workgroup
+candidate and loads in flight), visited-set size, wavefronts per workgroup
 -- on a sample of that bucket's queries and keeps the fastest. Results are
 cached in a JSON file keyed by device, storage type, dimension, metric, row
 width, bucket capacity and rerank mode.
@@ -25,7 +25,7 @@ def candidate_shapes(dtype: torch.dtype, d: int):
     elif d == 128 and dtype == torch.bfloat16:
         variants = (0, 3)
     return [dict(gather_variant=v, hash_log2=h, waves_per_block=w)
-            for v in variants for h in (0, 12) for w in (1, 2)]
+            for v in variants for h in (0, 11) for w in (1, 2)]
 
 
 def _key(base, metric, R, cap, rerank):
