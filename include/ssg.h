@@ -295,15 +295,17 @@ int ssg_nssg_reverse(const float* base, int64_t n, int32_t d, const uint32_t* g1
  *   ids, dists  DEVICE [S][nq][K] per-shard results (shard-local ids,
  *               SSG_SENTINEL / +inf padding), e.g. S ssg_search outputs
  *               written into consecutive slices
- *   id_map      DEVICE uint32: shard s's local id l is id_map[map_off[s] + l]
+ *   id_map      DEVICE uint32[map_len]: shard s's local id l is
+ *               id_map[map_off[s] + l]; a local id whose index falls outside
+ *               [0, map_len) is treated as padding
  *   map_off     DEVICE int64[S]
  *   out_ids, out_dists  DEVICE [nq][K_out]; padding where fewer than K_out
  *               real results exist
  * Requires S * K <= 4096 and K_out <= S * K. Asynchronous on stream.
  */
 int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t S, int64_t nq, int32_t K,
-                     const uint32_t* id_map, const int64_t* map_off, int32_t K_out,
-                     uint32_t* out_ids, float* out_dists, void* stream);
+                     const uint32_t* id_map, const int64_t* map_off, int64_t map_len,
+                     int32_t K_out, uint32_t* out_ids, float* out_dists, void* stream);
 
 /*
  * ssg_exact_ssg -- the exact satellite system graph (Alg. 2): for every node

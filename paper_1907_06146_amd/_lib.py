@@ -112,7 +112,7 @@ def lib() -> ctypes.CDLL:
             L.ssg_nssg_reverse_workspace_bytes.restype = sz
             L.ssg_nssg_reverse.argtypes = [P, i64, i32, P, i32, dbl, P, P, sz, P]
             L.ssg_nssg_reverse.restype = ctypes.c_int
-            L.ssg_merge_shards.argtypes = [P, P, i32, i64, i32, P, P, i32, P, P, P]
+            L.ssg_merge_shards.argtypes = [P, P, i32, i64, i32, P, P, i64, i32, P, P, P]
             L.ssg_merge_shards.restype = ctypes.c_int
             L.ssg_exact_ssg_workspace_bytes.argtypes = [i64]
             L.ssg_exact_ssg_workspace_bytes.restype = sz

@@ -47,6 +47,7 @@ struct MergeArgs {
   int K;
   const uint32_t* id_map;  // shard s, local id l -> id_map[map_off[s] + l]
   const int64_t* map_off;  // [S]
+  int64_t map_len;         // entries of id_map
   int K_out;
   uint32_t* out_ids;       // [nq][K_out]
   float* out_dists;        // [nq][K_out]
@@ -64,10 +65,11 @@ __global__ __launch_bounds__(64) void merge_kernel(MergeArgs a) {
     const int64_t src = ((int64_t)s * a.nq + q) * K + i;
     const uint32_t l = a.ids[src];
     uint64_t key;
-    if (l == kSent) {
-      key = ~0ull - (uint64_t)e;  // distinct, above every real key
+    const int64_t at = a.map_off[s] + (int64_t)l;
+    if (l == kSent || at < 0 || at >= a.map_len) {
+      key = ~0ull - (uint64_t)e;  // padding (or an id outside the map): above every real key
     } else {
-      const uint32_t g = a.id_map[a.map_off[s] + l];
+      const uint32_t g = a.id_map[at];
       key = ((uint64_t)ord_f32(a.dists[src]) << 32) | g;
     }
     raw[e] = key;
@@ -118,9 +120,11 @@ int fail_msg(int code, const char* fmt, ...) {
 
 extern "C" int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t S, int64_t nq,
                                 int32_t K, const uint32_t* id_map, const int64_t* map_off,
-                                int32_t K_out, uint32_t* out_ids, float* out_dists, void* stream) {
-  if (nq < 0 || S < 1 || K < 1 || K_out < 1)
-    return fail_msg(SSG_EINVAL, "ssg_merge_shards: S=%d K=%d K_out=%d nq=%lld", S, K, K_out, (long long)nq);
+                                int64_t map_len, int32_t K_out, uint32_t* out_ids, float* out_dists,
+                                void* stream) {
+  if (nq < 0 || S < 1 || K < 1 || K_out < 1 || map_len < 0)
+    return fail_msg(SSG_EINVAL, "ssg_merge_shards: S=%d K=%d K_out=%d nq=%lld map_len=%lld", S, K,
+                    K_out, (long long)nq, (long long)map_len);
   if ((int64_t)S * K > MAX_KEYS)
     return fail_msg(SSG_EUNSUPPORTED, "ssg_merge_shards: S * K = %d exceeds %d", S * K, MAX_KEYS);
   if (K_out > S * K) return fail_msg(SSG_EINVAL, "ssg_merge_shards: K_out above S * K");
@@ -128,7 +132,7 @@ extern "C" int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t
   if (!ids || !dists || !id_map || !map_off || !out_ids || !out_dists)
     return fail_msg(SSG_EINVAL, "ssg_merge_shards: null pointer argument");
   if (nq > 0x7FFFFFFF) return fail_msg(SSG_EINVAL, "ssg_merge_shards: nq too large for one launch");
-  MergeArgs a{ids, dists, S, nq, K, id_map, map_off, K_out, out_ids, out_dists};
+  MergeArgs a{ids, dists, S, nq, K, id_map, map_off, map_len, K_out, out_ids, out_dists};
   hipLaunchKernelGGL(merge_kernel, dim3((unsigned)nq), dim3(64), (size_t)16 * S * K,
                      static_cast<hipStream_t>(stream), a);
   if (hipGetLastError() != hipSuccess)

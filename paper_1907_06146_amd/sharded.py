@@ -99,7 +99,7 @@ class ShardedIndex:
         out_i = torch.empty((nq, K_out), dtype=torch.int32, device=dev)
         out_d = torch.empty((nq, K_out), dtype=torch.float32, device=dev)
         rc = _lib.lib().ssg_merge_shards(_ptr(ids), _ptr(dd), self.S, nq, K, _ptr(idmap),
-                                         _ptr(off), K_out, _ptr(out_i), _ptr(out_d),
+                                         _ptr(off), idmap.numel(), K_out, _ptr(out_i), _ptr(out_d),
                                          ctypes.c_void_p(main.cuda_stream))
         _lib.check(rc)
         # the shard buffers stay alive until the merge has read them

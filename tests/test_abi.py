@@ -140,8 +140,9 @@ def test_build_steps_reject_bad_arguments_on_host():
 def test_merge_shards_rejects_bad_arguments_on_host():
     keep, p = _fake()
     L = _lib.lib()
-    assert L.ssg_merge_shards(p, p, 0, 10, 5, p, p, 5, p, p, None) == _lib.SSG_EINVAL
-    assert L.ssg_merge_shards(p, p, 50, 10, 100, p, p, 5, p, p, None) == _lib.SSG_EUNSUPPORTED
-    assert L.ssg_merge_shards(p, p, 2, 10, 5, p, p, 11, p, p, None) == _lib.SSG_EINVAL
-    assert L.ssg_merge_shards(None, p, 2, 10, 5, p, p, 5, p, p, None) == _lib.SSG_EINVAL
-    assert L.ssg_merge_shards(None, None, 2, 0, 5, None, None, 5, None, None, None) == _lib.SSG_OK
+    assert L.ssg_merge_shards(p, p, 0, 10, 5, p, p, 100, 5, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(p, p, 50, 10, 100, p, p, 100, 5, p, p, None) == _lib.SSG_EUNSUPPORTED
+    assert L.ssg_merge_shards(p, p, 2, 10, 5, p, p, 100, 11, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(p, p, 2, 10, 5, p, p, -1, 5, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(None, p, 2, 10, 5, p, p, 100, 5, p, p, None) == _lib.SSG_EINVAL
+    assert L.ssg_merge_shards(None, None, 2, 0, 5, None, None, 0, 5, None, None, None) == _lib.SSG_OK

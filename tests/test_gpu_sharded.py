@@ -84,7 +84,7 @@ def test_merge_ties_and_padding():
     oi = torch.empty((nq, K_out), dtype=torch.int32, device="cuda")
     od = torch.empty((nq, K_out), dtype=torch.float32, device="cuda")
     tl, td, tm, to = _dev(loc), _dev(dist), _dev(idmap), _dev(off)
-    rc = _lib.lib().ssg_merge_shards(_ptr(tl), _ptr(td), S, nq, K, _ptr(tm), _ptr(to), K_out, _ptr(oi),
+    rc = _lib.lib().ssg_merge_shards(_ptr(tl), _ptr(td), S, nq, K, _ptr(tm), _ptr(to), len(idmap), K_out, _ptr(oi),
                                      _ptr(od), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     _lib.check(rc)
     torch.cuda.synchronize()
@@ -97,3 +97,28 @@ def test_merge_ties_and_padding():
         exp_d = [d for d, _ in real] + [np.inf] * (K_out - len(real))
         assert gi[r].tolist() == exp_i[:K_out]
         assert np.array_equal(gd[r], np.array(exp_d[:K_out], np.float32))
+
+
+def test_merge_treats_ids_outside_the_map_as_padding():
+    """A local id whose map index falls outside [0, map_len) is never read
+    through; it is padding."""
+    from paper_1907_06146_amd import _lib
+    from paper_1907_06146_amd.binding import _ptr
+    import ctypes
+    S, nq, K = 2, 1, 3
+    loc = np.array([[[0, 5, SENT]], [[1, 0, 2]]], np.uint32)     # 5 and 2 are past their maps
+    dist = np.array([[[1.0, 0.5, np.inf]], [[2.0, 3.0, 0.1]]], np.float32)
+    idmap = np.array([40, 41, 50, 51], np.uint32)                 # shard 0: 40, 41; shard 1: 50, 51
+    off = np.array([0, 2], np.int64)
+    K_out = 6
+    oi = torch.empty((nq, K_out), dtype=torch.int32, device="cuda")
+    od = torch.empty((nq, K_out), dtype=torch.float32, device="cuda")
+    tl, td, tm, to = _dev(loc), _dev(dist), _dev(idmap), _dev(off)
+    rc = _lib.lib().ssg_merge_shards(_ptr(tl), _ptr(td), S, nq, K, _ptr(tm), _ptr(to), len(idmap), K_out,
+                                     _ptr(oi), _ptr(od), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _lib.check(rc)
+    torch.cuda.synchronize()
+    gi, gd = oi.cpu().numpy().view(np.uint32)[0], od.cpu().numpy()[0]
+    # shard 0 local 5 -> index 5 >= 4: padding; shard 1 local 2 -> index 4 >= 4: padding
+    assert gi.tolist() == [40, 51, 50, SENT, SENT, SENT]
+    assert gd[:3].tolist() == [1.0, 2.0, 3.0] and np.isinf(gd[3:]).all()
