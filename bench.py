@@ -82,13 +82,14 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="gather shape variant")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / FP8 forms")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "build", "sharded", "alpha",
-                                                        "scaling", "exact"],
+                                                        "scaling", "exact", "shapes"],
                     help="c2: the headline search; c3: storage precisions on 960-d data; "
                          "c4: mixed L/K batched form; c5: serving; build: GPU index build "
                          "(kNN graph and Alg. 3's pruning loops) on the 1M x 128 set; sharded: "
                          "partitioned search over random shards on the 1M x 128 set; alpha: "
                          "minimum-angle sweep; scaling: build and search cost against n; exact: "
-                         "exact SSG (Alg. 2) degrees and greedy path lengths on 10,000 points")
+                         "exact SSG (Alg. 2) degrees and greedy path lengths on 10,000 points; "
+                         "shapes: launch-shape sweep of the headline search")
     ap.add_argument("--shards", type=int, default=4, help="sharded: number of shards")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
@@ -111,6 +112,9 @@ def main():
 
     if a.workload == "exact":
         print(json.dumps(bench_exact(a)), flush=True)
+        return
+    if a.workload == "shapes":
+        print(json.dumps(bench_shapes(a)), flush=True)
         return
     if a.workload in ("alpha", "scaling"):
         print(json.dumps(bench_alpha(a) if a.workload == "alpha" else bench_scaling(a)), flush=True)
@@ -869,6 +873,51 @@ def bench_serving(a):
     return {"metric": "serving queries/s and p50/p99 latency (BF16 + FP32 rerank, 1 GPU)",
             "index": f"{a.serve_data}: {len(base)} x {base.shape[1]}", "value": s["qps"],
             "unit": "queries/s", "n_gpus": 1, **s}
+
+def bench_shapes(a):
+    """Launch-shape sweep of the headline search (1M x 128, L = 80): gather
+    variant x visited-set size x waves per workgroup, FP32 and BF16 storage,
+    on the 10,000 queries and on them tiled 10 times. Every row's ids are
+    checked against the oracle's stored result."""
+    import torch
+    import synth
+    from paper_1907_06146_amd import graph_io, search, quantize
+    cfg = synth.CONFIGS[WORKLOAD]
+    gc = graph_io.load(WORKLOAD)
+    base = synth.base_vectors(cfg)
+    if synth.checksum(base) != gc["meta"]["base_sha"]:
+        raise SystemExit("regenerated base vectors do not match the graph cache")
+    q = synth.queries(cfg, base)
+    droot = os.path.join(graph_io.default_root(), WORKLOAD)
+    with open(os.path.join(droot, "sweep.json")) as f:
+        L = a.L or json.load(f)["L_op"]
+    K = cfg["K"]
+    oi = np.load(os.path.join(droot, f"oracle_L{L}_ids.npy"), allow_pickle=False)
+    dev = torch.device("cuda:0")
+    tb = torch.from_numpy(base).to(dev)
+    tg = graph_io.to_device(gc["graph"], dev)
+    te = graph_io.to_device(gc["entry_ids"], dev)
+    qb, _ = quantize(tb, "bf16")
+    stream = torch.cuda.current_stream(dev)
+    plan = [("f32", v, hl, w) for v in (0, 1, 2, 3, 4, 6) for hl in (11, 12) for w in (1, 2)]
+    plan += [("bf16", 0, hl, w) for hl in (11, 12) for w in (1, 2)]
+    rows = []
+    for tile in (1, 10):
+        tq = torch.from_numpy(np.tile(q, (tile, 1))).to(dev)
+        ids = torch.empty((len(tq), K), dtype=torch.int32, device=dev)
+        dd = torch.empty((len(tq), K), dtype=torch.float32, device=dev)
+        for dt, var, hl, wpb in plan:
+            kw = dict(out=(ids, dd), gather_variant=var, hash_log2=hl, waves_per_block=wpb)
+            bse = tb if dt == "f32" else qb
+            ms = _time(lambda: search(bse, tg, te, tq, K, L, **kw), 10 if tile == 1 else 3, 2, stream)
+            same = bool(np.array_equal(ids[:len(q)].cpu().numpy().view(np.uint32), oi))
+            r = dict(queries=len(tq), dtype=dt, variant=var, hash_log2=hl, waves_per_block=wpb,
+                     ms=ms, qps=len(tq) / ms * 1e3, ids_equal_oracle=same)
+            log(f"shapes: {r}")
+            rows.append(r)
+    return {"metric": "launch-shape sweep of the 1M x 128 search (L = %d, K = %d)" % (L, K),
+            "unit": "ms per launch", "rows": rows, "data": "synthetic (seeded)"}
+
 
 def cpu_baseline(base, gc, q, K, L, cfg, sample):
     """The FP64 CPU oracle (Alg. 1, all host threads) on a bounded sample of

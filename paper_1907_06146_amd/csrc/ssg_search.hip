@@ -336,95 +336,110 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     return fmaf(df, df, acc);
   };
 
-  // distances of the candidates in bids[0..m) -> bkeys[0..m)
-  auto batch_keys = [&](int m) {
-    for (int c0 = 0; c0 < m; c0 += CPP * NP) {
-      uint32_t idp[NP];
-      bool vp[NP];
+  // One gather pass covers candidates c0 + p * CPP + grp (p < NP) of
+  // bids[0..m): `issue` reads their ids and, on the compiled path, starts
+  // every load of the pass; `finish` turns the loaded rows into keys in
+  // bkeys. Between the two the loads are in flight.
+  struct Pass {
+    uint4 buf[NP][kCompiled ? NCH : 1];
+    uint32_t idp[NP];
+    bool vp[NP];
+  };
+  auto issue = [&](Pass& ps, int c0, int m) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int c = c0 + p * CPP + grp;
+      ps.vp[p] = c < m;
+      ps.idp[p] = ps.vp[p] ? bids[c] : 0u;
+    }
+    if constexpr (kCompiled) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const int c = c0 + p * CPP + grp;
-        vp[p] = c < m;
-        idp[p] = vp[p] ? bids[c] : 0u;
-      }
-      float acc[NP];
+        const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)ps.idp[p] * a.dc * 16);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) acc[p] = 0.f;
-      if constexpr (kCompiled) {
-        // with the query in LDS, re-read it per pass instead of letting the
-        // compiler keep a register copy (the point is to free those registers)
-        if constexpr (!kQueryInRegs) __asm__ volatile("" ::: "memory");
-        uint4 buf[NP][NCH];
+        for (int t = 0; t < NCH; ++t) {
+          // lanes past the batch read row 0 (idp = 0) and their sums are
+          // discarded; loading unconditionally avoids zeroing the registers
+          const int ch = g + G * t;
+          if (DC % G == 0 || ch < DC) ps.buf[p][t] = vec[ch];
+          else ps.buf[p][t] = make_uint4(0, 0, 0, 0);
+        }
+      }
+    }
+  };
+  auto finish = [&](Pass& ps, int c0) {
+    float acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+    if constexpr (kCompiled) {
+      // with the query in LDS, re-read it per pass instead of letting the
+      // compiler keep a register copy (the point is to free those registers)
+      if constexpr (!kQueryInRegs) __asm__ volatile("" ::: "memory");
+      // the metric is uniform: branch once per pass, not per element
+      auto accumulate = [&](auto ip_c) {
+        constexpr bool IP = decltype(ip_c)::value;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-          const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)idp[p] * a.dc * 16);
 #pragma unroll
           for (int t = 0; t < NCH; ++t) {
-            // lanes past the batch read row 0 (idp = 0) and their sums are
-            // discarded; loading unconditionally avoids zeroing the registers
             const int ch = g + G * t;
-            if (DC % G == 0 || ch < DC) buf[p][t] = vec[ch];
-            else buf[p][t] = make_uint4(0, 0, 0, 0);
-          }
-        }
-        // the metric is uniform: branch once per pass, not per element
-        auto accumulate = [&](auto ip_c) {
-          constexpr bool IP = decltype(ip_c)::value;
+            if (DC % G == 0 || ch < DC) {
+              float x[EPC];
+              T::decode(ps.buf[p][t], x);
 #pragma unroll
-          for (int p = 0; p < NP; ++p) {
-#pragma unroll
-            for (int t = 0; t < NCH; ++t) {
-              const int ch = g + G * t;
-              if (DC % G == 0 || ch < DC) {
-                float x[EPC];
-                T::decode(buf[p][t], x);
-#pragma unroll
-                for (int e = 0; e < EPC; ++e) {
-                  float sv, qv;
-                  if constexpr (kQueryInRegs) {
-                    sv = kScaled ? sf[t * EPC + e] : 1.f;
-                    qv = qf[t * EPC + e];
-                  } else {
-                    sv = kScaled ? qlds[a.d + ch * EPC + e] : 1.f;
-                    qv = qlds[ch * EPC + e];
-                  }
-                  const float xv = kScaled ? __fmul_rn(x[e], sv) : x[e];
-                  if constexpr (IP) {
-                    acc[p] = fmaf(qv, xv, acc[p]);
-                  } else {
-                    const float df = qv - xv;
-                    acc[p] = fmaf(df, df, acc[p]);
-                  }
+              for (int e = 0; e < EPC; ++e) {
+                float sv, qv;
+                if constexpr (kQueryInRegs) {
+                  sv = kScaled ? sf[t * EPC + e] : 1.f;
+                  qv = qf[t * EPC + e];
+                } else {
+                  sv = kScaled ? qlds[a.d + ch * EPC + e] : 1.f;
+                  qv = qlds[ch * EPC + e];
+                }
+                const float xv = kScaled ? __fmul_rn(x[e], sv) : x[e];
+                if constexpr (IP) {
+                  acc[p] = fmaf(qv, xv, acc[p]);
+                } else {
+                  const float df = qv - xv;
+                  acc[p] = fmaf(df, df, acc[p]);
                 }
               }
             }
           }
-        };
-        if (ip) accumulate(std::true_type{});
-        else accumulate(std::false_type{});
-      } else {
+        }
+      };
+      if (ip) accumulate(std::true_type{});
+      else accumulate(std::false_type{});
+    } else {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (vp[p]) {
-            const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)idp[p] * a.dc * 16);
+      for (int p = 0; p < NP; ++p) {
+        if (ps.vp[p]) {
+          const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)ps.idp[p] * a.dc * 16);
 #pragma unroll 4
-            for (int ch = g; ch < a.dc; ch += G) {
-              float x[EPC];
-              T::decode(vec[ch], x);
+          for (int ch = g; ch < a.dc; ch += G) {
+            float x[EPC];
+            T::decode(vec[ch], x);
 #pragma unroll
-              for (int e = 0; e < EPC; ++e) {
-                const float xv = kScaled ? __fmul_rn(x[e], qlds[a.d + ch * EPC + e]) : x[e];
-                acc[p] = term(acc[p], qlds[ch * EPC + e], xv);
-              }
+            for (int e = 0; e < EPC; ++e) {
+              const float xv = kScaled ? __fmul_rn(x[e], qlds[a.d + ch * EPC + e]) : x[e];
+              acc[p] = term(acc[p], qlds[ch * EPC + e], xv);
             }
           }
         }
       }
+    }
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        acc[p] = group_sum<G>(acc[p], lane);
-        if (vp[p] && g == 0) bkeys[c0 + p * CPP + grp] = make_key(ip ? -acc[p] : acc[p], idp[p]);
-      }
+    for (int p = 0; p < NP; ++p) {
+      acc[p] = group_sum<G>(acc[p], lane);
+      if (ps.vp[p] && g == 0) bkeys[c0 + p * CPP + grp] = make_key(ip ? -acc[p] : acc[p], ps.idp[p]);
+    }
+  };
+  // keys of bids[first * CPP * NP .. m) (the passes before `first` are done)
+  auto batch_keys = [&](int m, int first = 0) {
+    for (int c0 = first * CPP * NP; c0 < m; c0 += CPP * NP) {
+      Pass ps;
+      issue(ps, c0, m);
+      finish(ps, c0);
     }
     wave_sync();
   };
@@ -490,13 +505,18 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     hcount = 1;
     wave_sync();
   }
-  uint32_t nb = lane < R ? a.graph[(size_t)p * R + lane] : kSent;  // row being expanded
-
-  for (;;) {
-    ++hops;
-    if (hops > a.n + 1) break;  // cannot happen (each node is expanded at most once); bounds the loop
-
-    // visited table maintenance: rebuild from the pool when half full
+  // Staging an expansion: its row's ids go through the visited set, the new
+  // ones are compacted into bids and the first gather pass is issued. The
+  // loop stages the next expansion before merging the current one, so that
+  // merge runs while the next gathers are in flight
+  // (only where the staged pass is at most 8 chunks per lane: its registers
+  // stay live across the merge)
+  constexpr bool kPipe = kCompiled && NP * NCH <= 8;
+  Pass pend;
+  int pm = 0;  // candidates of the staged expansion
+  auto stage_row = [&](uint32_t nb) {
+    // hash form: rebuild from the pool when half full (the keys of the batch
+    // being merged may be forgotten; the duplicate check below covers them)
     if (a.vmode == 1 && hcount + R > hlimit) {
       for (int i = lane; i <= (int)hmask; i += 64) table[i] = kSent;
       wave_sync();
@@ -506,6 +526,19 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       wave_sync();
       hcount = size;
     }
+    const bool fresh = nb != kSent && visit(nb);
+    const uint64_t fm = __ballot(fresh);
+    pm = __popcll(fm);
+    if (fresh) bids[lane_prefix(fm)] = nb;
+    wave_sync();
+    hcount += pm;
+    if (kPipe && pm > 0) issue(pend, 0, pm);
+  };
+  stage_row(lane < R ? a.graph[(size_t)p * R + lane] : kSent);
+
+  for (;;) {
+    ++hops;
+    if (hops > a.n + 1) break;  // cannot happen (each node is expanded at most once); bounds the loop
 
     // speculation: the first unchecked pool entry is the next expansion unless
     // a new key beats it; read its row now, alongside this hop's gathers
@@ -519,18 +552,13 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     const uint32_t nb_spec =
         u_spec != kNoKey && lane < R ? a.graph[(size_t)key_id(u_spec) * R + lane] : kSent;
 
-    // visited filter and compaction of the row's new ids
-    const bool fresh = nb != kSent && visit(nb);
-    const uint64_t fm = __ballot(fresh);
-    const int m = __popcll(fm);
-    if (fresh) bids[lane_prefix(fm)] = nb;
-    wave_sync();
-    hcount += m;
+    // keys of the staged expansion's new ids
+    const int m = pm;
     ndc += m;
-
     uint64_t b = kNoKey;
     if (m > 0) {
-      batch_keys(m);
+      if constexpr (kPipe) finish(pend, 0);
+      batch_keys(m, kPipe ? 1 : 0);
       b = lane < m ? bkeys[lane] : kNoKey;
       if (size == L) {
         // a new key above the L-th pool key would land at position >= L and be
@@ -541,9 +569,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
           if (k == ((L - 1) >> 6)) worst = readlane64(pool[k], (L - 1) & 63);
         if (b > worst) b = kNoKey;
       }
-      if (a.vmode == 2) {
-        // a pool member the cache forgot comes back with its pool key (up to
-        // the checked bit); drop it so the pool never holds an id twice
+      if (a.vmode != 0) {
+        // a pool member the visited set forgot comes back with its pool key
+        // (up to the checked bit); drop it so the pool never holds an id twice
         // (an id decides it: equal ids have equal keys; the low word of a key
         // is id << 1 | checked, and ids stay below 2^31 - 1)
         uint32_t plo[PREG];
@@ -561,10 +589,10 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     }
     const uint64_t bm = __ballot(b != kNoKey);  // new keys that can enter the pool
 
-    // next expansion, decided before the merge so its row read overlaps it:
-    // the smallest unchecked key u of (pool + new keys) is kept iff fewer
-    // than L keys precede it; otherwise every kept entry is checked. When no
-    // new key is below u_spec, u_spec keeps its pool position (< L).
+    // next expansion, decided before the merge: the smallest unchecked key u
+    // of (pool + new keys) is kept iff fewer than L keys precede it;
+    // otherwise every kept entry is checked. When no new key is below
+    // u_spec, u_spec keeps its pool position (< L).
     bool more = u != kNoKey;
     if (__ballot(b < u)) {
       u = wave_min64(b);  // below u_spec, so the smallest unchecked key
@@ -573,8 +601,12 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
       more = rank_u < L;
     }
-    uint32_t nb_next = nb_spec;
-    if (more && u != u_spec) nb_next = lane < R ? a.graph[(size_t)key_id(u) * R + lane] : kSent;
+    if (more) {
+      // stage it now: its gathers overlap the merge below
+      const uint32_t nb_next =
+          u == u_spec ? nb_spec : lane < R ? a.graph[(size_t)key_id(u) * R + lane] : kSent;
+      stage_row(nb_next);
+    }
 
     // rank-based merge of the surviving new keys into the pool, truncated to L
     if (bm) {
@@ -613,7 +645,6 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
 #pragma unroll
     for (int k = 0; k < PREG; ++k)
       if (pool[k] == u) pool[k] |= 1ull;  // mark the next expansion checked
-    nb = nb_next;
   }
 
   // ---- optional rerank: exact FP32 keys of the first `rerank` pool entries
@@ -883,12 +914,14 @@ struct Table<F32T> {
       case 32:                                                     // d = 128
         switch (variant) {
           case 1: l.fn = pick_preg<F32T, 32, 8, 1>(preg, batched); return l;  // 8 in flight
-          case 2: l.fn = pick_preg<F32T, 32, 8, 2>(preg, batched); return l;  // 16
+          case 2: l.fn = pick_preg<F32T, 32, 4, 1>(preg, batched); return l;  // 16
           case 3: l.fn = pick_preg<F32T, 32, 4, 2>(preg, batched); return l;  // 32
           case 4: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 4, 1, true>(preg, batched); return l;
           case 5: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 4, 2, true>(preg, batched); return l;
           case 6: l.query_in_regs = false; l.fn = pick_preg<F32T, 32, 8, 2, true>(preg, batched); return l;
-          default: l.fn = pick_preg<F32T, 32, 4, 1>(preg, batched); return l; // 16
+          // 8 lanes per candidate, 2 passes (16 in flight): the staged pass
+          // stays within 120 VGPRs (4 waves per SIMD) at L <= 256
+          default: l.fn = pick_preg<F32T, 32, 8, 2>(preg, batched); return l;
         }
       case 75: l.fn = pick_preg<F32T, 75, 16, 2>(preg, batched); return l;  // d = 300: 8
       case 240: l.fn = pick_preg<F32T, 240, 32, 4>(preg, batched); return l;  // d = 960: 8
