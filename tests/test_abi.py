@@ -146,3 +146,28 @@ def test_merge_shards_rejects_bad_arguments_on_host():
     assert L.ssg_merge_shards(p, p, 2, 10, 5, p, p, -1, 5, p, p, None) == _lib.SSG_EINVAL
     assert L.ssg_merge_shards(None, p, 2, 10, 5, p, p, 100, 5, p, p, None) == _lib.SSG_EINVAL
     assert L.ssg_merge_shards(None, None, 2, 0, 5, None, None, 0, 5, None, None, None) == _lib.SSG_OK
+
+
+def _call_ex(n=100, **opts):
+    keep, p = _fake()
+    o = _lib.SearchOpts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    return _lib.lib().ssg_search_ex(p, n, 32, 0, None, p, 8, p, 2, p, 4, 10, 20, 0, p, p,
+                                    ctypes.byref(o), None)
+
+
+@pytest.mark.parametrize("n,opts,code", [
+    (100, dict(visited_kind=4), _lib.SSG_EINVAL),
+    (100, dict(visited_kind=-1), _lib.SSG_EINVAL),
+    (100, dict(hash_log2=3), _lib.SSG_EINVAL),
+    (100, dict(hash_log2=16), _lib.SSG_EINVAL),
+    # a 16-bit tag cannot hold ids of 2^30 nodes with 1,024 sets: the cache
+    # form is refused when asked for explicitly (the default falls back to the hash)
+    (1 << 30, dict(visited_kind=2, hash_log2=12), _lib.SSG_EUNSUPPORTED),
+    (1 << 20, dict(exact_visited=1), _lib.SSG_EUNSUPPORTED),
+    (100, dict(entry_group_size=-1), _lib.SSG_EINVAL),
+])
+def test_search_options_rejected_on_host(n, opts, code):
+    assert _call_ex(n, **opts) == code
+    assert len(_lib.last_error()) > 0
