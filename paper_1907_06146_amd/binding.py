@@ -88,6 +88,8 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
         if entry_ids.dim() != 2 or entry_ids.shape[0] * entry_group_size < nq:
             raise ValueError("entry_group_size needs entry_ids of shape [groups, s] covering every query")
         n_entry = entry_ids.shape[1]
+    if visited not in _VISITED:
+        raise ValueError(f"visited must be one of {sorted(_VISITED)}, not {visited!r}")
     opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
                            None if ndc is None else ndc.data_ptr(),
                            None if hops is None else hops.data_ptr(), gather_variant,
