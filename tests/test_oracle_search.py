@@ -6,7 +6,9 @@
 * the independent pure-Python twin gives the same ids, keys, NDC and hops;
 * permuting graph rows changes nothing (set semantics of the add-then-sort step);
 * forgetting nodes once they leave the pool changes no result;
-* (dist, id) tie order (the tie rule used in the proof of Theorem 3).
+* (dist, id) tie order (the tie rule used in the proof of Theorem 3);
+* on a unit-norm base, inner-product search follows the L2 trajectory
+  (algebraic identity |q - x|^2 = |q|^2 + 1 - 2<q, x>).
 """
 
 import json
@@ -171,3 +173,26 @@ def test_bad_arguments_raise():
         core.search(base, g, [7], base[:1], 1, 1)  # entry id out of range
     with pytest.raises(ValueError):
         core.search(base, g, [0], base[:1], 0, 1)  # K < 1
+
+
+def test_inner_product_on_unit_norm_base_equals_l2(c1_graph):
+    """On a unit-norm base, |q - x|^2 = |q|^2 + 1 - 2<q, x>, so L2 and -IP
+    order the candidates alike: Alg. 1 follows the same trajectory and the
+    returned keys satisfy that identity (pins the IP key's sign and form)."""
+    base, q, g, entry, _, _ = c1_graph
+    b = base.astype(np.float64)
+    b /= np.linalg.norm(b, axis=1, keepdims=True)
+    b = b.astype(np.float32)
+    i2, d2, n2, h2 = core.search(b, g, entry, q, 10, 50, "l2")
+    ii, di, ni, hi = core.search(b, g, entry, q, 10, 50, "ip")
+    same = (i2 == ii).all(1)
+    assert same.mean() > 0.99
+    qq = (q.astype(np.float64) ** 2).sum(1)[:, None]
+    xx = (b.astype(np.float64) ** 2).sum(1)  # 1 up to the fp32 rounding of the rows
+    # dists of the IP search, converted with the identity, agree with the
+    # L2 search's (rows that differ may only do so through near-equal keys)
+    conv = qq + xx[ii.astype(np.int64)] + 2.0 * di
+    assert np.allclose(conv[same], d2[same], rtol=1e-12, atol=1e-12)
+    assert np.allclose(np.sort(d2[~same], 1), np.sort(qq[~same] + 1.0 + 2.0 * di[~same], 1),
+                       rtol=1e-6, atol=1e-6)
+    assert np.array_equal(h2[same], hi[same])
