@@ -846,8 +846,13 @@ def bench_serving(a):
     warm, _ = poisson_requests(np.random.default_rng(1), 50, 1e6, q, [64], scfg["K"], max_batch=64)
     if a.serve_mode == "batch":
         n_slots, max_batch = 3, 8192
+        # --hash-log2 / --waves-per-block, when given, set every bucket's launch shape
+        shapes = None
+        if a.hash_log2 or a.waves_per_block:
+            shapes = {cap: {"hash_log2": a.hash_log2, "waves_per_block": a.waves_per_block}
+                      for cap in (64, 128, 256, 512)}
         gdev = GpuBatchDevice(qb, tg, te, n_slots=n_slots, max_batch=max_batch, max_K=scfg["K"],
-                              metric="ip", base_f32=tb, rerank=True)
+                              metric="ip", base_f32=tb, rerank=True, shapes=shapes)
         run(warm, BatchScheduler(gdev, n_slots, max_batch))
         sch = BatchScheduler(gdev, n_slots=n_slots, max_batch=max_batch)
     else:
