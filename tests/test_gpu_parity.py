@@ -150,6 +150,19 @@ def test_c1_pool_sizes_and_large_k(c1_graph, L):
     assert (gi[:, L:] == SENT).all() and np.isinf(gd[:, L:]).all()
 
 
+def test_largest_result_count_and_pool(c1_graph):
+    """K at its maximum (4096) with the largest pool (512): every row holds
+    the pool's 512 entries, then padding."""
+    base, q, g, entry, _, _ = c1_graph
+    K, L = 4096, 512
+    q = q[:16]
+    oi, od, _, ohops = core.search(base, g, entry, q, K, L)
+    gi, gd, _, ghops = _gpu(base, g, entry, q, K, L)
+    _compare(base, q, gi, gd, oi, od, min_match=0.9)
+    assert (gi[:, L:] == SENT).all() and np.isinf(gd[:, L:]).all()
+    assert (gi[:, :L] != SENT).all()
+
+
 def test_inner_product_unit_norm():
     cfg = synth.CONFIGS["c4s"]
     base = synth.base_vectors(cfg)
@@ -192,6 +205,10 @@ def test_edge_cases():
             gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, exact_visited=True)
             assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od)
             assert np.array_equal(gndc, ondc) and np.array_equal(ghops, ohops)
+            for form, hl in (("hash", 0), ("cache", 0), ("cache", 4)):
+                gi, gd, gndc, ghops = _gpu(base, g, entry, q, K, L, visited=form, hash_log2=hl)
+                assert np.array_equal(gi, oi) and np.array_equal(gd.astype(np.float64), od), form
+                assert np.array_equal(ghops, ohops) and (gndc >= ondc).all(), form
     # no queries
     from paper_1907_06146_amd import search
     ids, dd = search(_dev(base), _dev(g), _dev(np.array([0], np.uint32)),
