@@ -186,6 +186,8 @@ typedef struct {
     int32_t hash_log2;         /* 0 = default */
     int32_t waves_per_block;   /* 0 = default */
     int32_t blocks;            /* persistent grid size; 0 = fill the GPU once */
+    int32_t visited_kind;      /* visited-set form, as ssg_search_opts.visited_kind
+                                  (0 default, 1 hash, 2 tag cache) */
 } ssg_bucket;
 
 /* Workspace for nb buckets (one work-queue counter each). */

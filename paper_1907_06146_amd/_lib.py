@@ -59,7 +59,8 @@ class BatchDesc(ctypes.Structure):
 class Bucket(ctypes.Structure):
     _fields_ = [("qlist", ctypes.c_void_p), ("count", ctypes.c_int64), ("max_L", ctypes.c_int32),
                 ("gather_variant", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("visited_kind", ctypes.c_int32)]
 
 
 _lock = threading.Lock()

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .binding import _DTYPES, _METRICS, _need_cuda
+from .binding import _DTYPES, _METRICS, _VISITED, _need_cuda
 
 BUCKET_BOUNDS = (64, 128, 256, 512)
 
@@ -45,7 +45,8 @@ class BatchedSearch:
     base / base_f32 / dim_scale as in ``search``; L, K: int32 [nq] (host or
     device); rerank: 0 none, -1 the first K_i entries, > 0 a fixed count.
     shapes: {max_L bucket capacity: dict(gather_variant, hash_log2,
-    waves_per_block, blocks)} from the autotuner.
+    waves_per_block, blocks, visited)} from the autotuner (visited: "auto",
+    "hash" or "cache", the form of the LDS visited set).
     """
 
     def __init__(self, base, graph, entry_ids, queries, L, K, metric="l2", dim_scale=None,
@@ -90,7 +91,7 @@ class BatchedSearch:
             sh = shapes.get(cap, {})
             arr[i] = _lib.Bucket(ql.data_ptr(), len(q), mL, sh.get("gather_variant", 0),
                                  sh.get("hash_log2", 0), sh.get("waves_per_block", 0),
-                                 sh.get("blocks", 0))
+                                 sh.get("blocks", 0), _VISITED[sh.get("visited", "auto")])
         self.buckets = arr
         self.graph = None
         if use_graph:

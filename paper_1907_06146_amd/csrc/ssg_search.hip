@@ -1276,8 +1276,10 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     BucketLaunch bl{};
     Args& a = bl.a;
     VisitedPlan vp;
-    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, 0, D->n, D->base_f32 != nullptr,
-                    b.hash_log2, &vp);
+    if (b.visited_kind < 0 || b.visited_kind > 2)
+      return fail(SSG_EINVAL, "bucket %d: visited_kind must be 0, 1 or 2", i);
+    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, b.visited_kind, D->n,
+                    D->base_f32 != nullptr, b.hash_log2, &vp);
     if (rc) return rc;
     a.vmode = vp.vmode;
     a.hash_log2 = vp.hash_log2;

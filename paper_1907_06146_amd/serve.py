@@ -315,8 +315,9 @@ class GpuBatchDevice:
 
         from . import _lib
         from .batched import BUCKET_BOUNDS
-        from .binding import _DTYPES, _METRICS
+        from .binding import _DTYPES, _METRICS, _VISITED
         self.torch, self.ctypes, self.lib_mod = torch, ctypes, _lib
+        self.visited_map = _VISITED
         self.bounds = BUCKET_BOUNDS
         self.index = (base, graph, entry_ids, dim_scale, base_f32)
         self.dtype, self.metric = _DTYPES[base.dtype], _METRICS[metric]
@@ -384,7 +385,8 @@ class GpuBatchDevice:
                 sh = self.shapes.get(cap, {})
                 arr[i] = _lib.Bucket(dLK[2].data_ptr() + 4 * off, len(qi), mL,
                                      sh.get("gather_variant", 0), sh.get("hash_log2", 0),
-                                     sh.get("waves_per_block", 0), sh.get("blocks", 0))
+                                     sh.get("waves_per_block", 0), sh.get("blocks", 0),
+                                     self.visited_map[sh.get("visited", "auto")])
             _lib.check(_lib.lib().ssg_search_batched(ctypes.byref(desc), arr, len(plan),
                                                      ctypes.c_void_p(s["wsp"]), s["wsb"],
                                                      ctypes.c_void_p(s["stream"].cuda_stream)))

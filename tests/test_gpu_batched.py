@@ -61,6 +61,29 @@ def test_mixed_batch_matches_oracle(c4s):
     bs.close()
 
 
+@pytest.mark.parametrize("form", ["hash", "cache"])
+def test_mixed_batch_with_a_forgetful_visited_set(c4s, form):
+    """The persistent batched kernel with tiny visited tables (16-entry cache,
+    or the smallest hash, which is rebuilt often): returning pool members are
+    dropped, so every row and hop count equals the default launch's."""
+    from paper_1907_06146_amd.batched import BatchedSearch
+    cfg, base, q, g, entry, Lq, Kq = c4s
+    args = (_dev(base), _dev(g), _dev(entry), _dev(q), Lq, Kq, "ip")
+    ref = BatchedSearch(*args, stats=True, use_graph=False)
+    ri, rd = ref.run()
+    torch.cuda.synchronize()
+    ri, rd, rh = ri.cpu().numpy().copy(), rd.cpu().numpy().copy(), ref.hops.cpu().numpy().copy()
+    hl = 4 if form == "cache" else 0
+    shapes = {cap: {"hash_log2": hl, "visited": form} for cap in (64, 128, 256, 512)}
+    bs = BatchedSearch(*args, stats=True, use_graph=False, shapes=shapes)
+    gi, gd = bs.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(gi.cpu().numpy(), ri) and np.array_equal(gd.cpu().numpy(), rd)
+    assert np.array_equal(bs.hops.cpu().numpy(), rh)
+    ref.close()
+    bs.close()
+
+
 def test_graph_replays_equal_eager(c4s):
     from paper_1907_06146_amd.batched import BatchedSearch
     cfg, base, q, g, entry, Lq, Kq = c4s
