@@ -57,7 +57,7 @@ def lib():
             L.orc_threads.argtypes = [i32]
             L.orc_threads.restype = i32
             L.orc_search.argtypes = [P, i64, i32, P, i32, P, i32, P, i64, i32, i32, P, P, i32,
-                                     i32, P, P, P, P]
+                                     i32, P, P, P, P, P, i32]
             L.orc_ssg_exact.argtypes = [P, i64, i32, f64, i32, P, P]
             L.orc_pair_keys.argtypes = [P, i64, i32, P, i64, P, i32, i32, P]
             L.orc_knn_refine.argtypes = [P, i64, i32, P, i32, i32, P]
@@ -196,19 +196,15 @@ def knn_graph(base, K: int, **kw):
     return topk(base, base, K, "l2", exclude_self=True, **kw)
 
 
-def knn_graph_ivf(base, K: int, nlist: int, nprobe: int, seed: int, iters: int = 6,
-                  sample: int = 100_000, margin: int = 16, verbose: bool = False):
-    """Approximate K-nearest-neighbour graph for the large workloads (step 1
-    of Alg. 3 asks only for an approximate kNN graph; the paper uses
-    nn-descent, or an IVF index in Alg. 4).
+def ivf_partition(base, nlist: int, nprobe: int, seed: int, iters: int = 6,
+                  sample: int = 100_000):
+    """Cells and probe lists of the IVF candidate pass of ``knn_graph_ivf``.
 
-    The base set is split into nlist cells by k-means (Lloyd iterations on a
-    seeded sample). The candidates of every point of cell c are the points of
-    the nprobe cells whose centroids are nearest to c's centroid; a coarse
-    fp32 pass keeps K + margin of them and the C oracle picks the K nearest by
-    exact FP64 keys, in (dist, id) order. Points the probe misses are the only
-    source of error; ``knn_accuracy`` measures it against a full scan.
-    """
+    k-means (Lloyd iterations on a seeded sample of at most ``sample`` rows)
+    gives nlist centroids; every point is assigned to its nearest centroid
+    (fp32 scores); cell c probes the nprobe cells whose centroids are nearest
+    to c's centroid (FP64 scores). Returns (labels[n] int64,
+    probe[nlist, nprobe] int64, centroids float32 [nlist, d])."""
     import torch
 
     base = _f32(base)
@@ -227,18 +223,42 @@ def knn_graph_ivf(base, K: int, nlist: int, nprobe: int, seed: int, iters: int =
             out[lo:lo + 65536] = s.argmin(1)
         return out
 
-    for it in range(iters):
+    for _ in range(iters):
         a = assign(samp)
         sums = torch.zeros_like(cent).index_add_(0, a, samp)
         cnt = torch.bincount(a, minlength=nlist).float()
         keep = cnt > 0
         cent[keep] = sums[keep] / cnt[keep, None]
     lab = assign(tb).numpy()
-    order = np.argsort(lab, kind="stable")
-    starts = np.searchsorted(lab[order], np.arange(nlist + 1))
     cn = (cent.double() ** 2).sum(1)
     cd = cn[:, None] + cn[None, :] - 2.0 * (cent.double() @ cent.double().t())
     probe = torch.topk(cd, min(nprobe, nlist), dim=1, largest=False).indices.numpy()
+    return lab, probe, cent.numpy()
+
+
+def knn_graph_ivf(base, K: int, nlist: int, nprobe: int, seed: int, iters: int = 6,
+                  sample: int = 100_000, margin: int = 16, verbose: bool = False):
+    """Approximate K-nearest-neighbour graph for the large workloads (step 1
+    of Alg. 3 asks only for an approximate kNN graph; the paper uses
+    nn-descent, or an IVF index in Alg. 4).
+
+    The base set is split into cells by ``ivf_partition``. The candidates of
+    every point of cell c are the points of the cells c probes; a coarse fp32
+    pass keeps K + margin + 1 of them and the C oracle picks the K nearest
+    other points by exact FP64 keys, in (dist, id) order. Points outside the
+    probed cells are the only source of error (``knn_accuracy`` measures it
+    against a full scan); with nprobe = nlist the result is the exact kNN
+    graph whenever the coarse pass keeps the true K nearest (always, for
+    integer data, where the fp32 scores are exact).
+    """
+    import torch
+
+    base = _f32(base)
+    n, d = base.shape
+    tb = torch.from_numpy(base)
+    lab, probe, _ = ivf_partition(base, nlist, nprobe, seed, iters, sample)
+    order = np.argsort(lab, kind="stable")
+    starts = np.searchsorted(lab[order], np.arange(nlist + 1))
     ny = (tb.double() ** 2).sum(1).float()
     C = K + margin + 1
     cand = np.full((n, C), -1, np.int64)
@@ -356,12 +376,14 @@ def threads(n: int = 0) -> int:
 
 
 def search(base, graph, entry_ids, Q, K: int, L: int, metric: str = "l2", forget: bool = False,
-           seed_all: bool = False, L_arr=None, K_arr=None):
+           seed_all: bool = False, L_arr=None, K_arr=None, trace: int = 0):
     """Alg. 1 (Search-on-Graph) from the navigating node nearest each query.
 
     Returns (ids[nq, K] uint32, dists[nq, K] float64, ndc[nq], hops[nq]);
     rows hold the first min(K, |S|) pool entries, padded with 0xFFFFFFFF and
     +inf. With per-query ``L_arr``/``K_arr`` the output stride is K = max.
+    trace > 0 appends trace[nq, trace] uint32: the ids of the first `trace`
+    expanded nodes of each query in expansion order, padded with 0xFFFFFFFF.
     """
     base, Q = _f32(base), _f32(Q)
     graph = np.ascontiguousarray(graph, dtype=np.uint32)
@@ -375,11 +397,14 @@ def search(base, graph, entry_ids, Q, K: int, L: int, metric: str = "l2", forget
     ndc = np.empty(nq, np.int64)
     hops = np.empty(nq, np.int64)
     flags = (1 if forget else 0) | (2 if seed_all else 0)
+    tr = np.empty((nq, trace), np.uint32) if trace > 0 else None
     rc = lib().orc_search(_p(base), n, d, _p(graph), graph.shape[1], _p(entry), len(entry), _p(Q),
                           nq, K, L, _p(La), _p(Ka), METRICS[metric], flags, _p(ids), _p(dd),
-                          _p(ndc), _p(hops))
+                          _p(ndc), _p(hops), _p(tr), int(trace))
     if rc:
         raise ValueError(f"orc_search rc={rc}")
+    if tr is not None:
+        return ids, dd, ndc, hops, tr
     return ids, dd, ndc, hops
 
 

@@ -25,8 +25,10 @@ def _key(q, x, metric):
     return -s
 
 
-def search(base, graph, entry_ids, q, K, L, metric="l2"):
-    """Alg. 1 from the navigating node nearest q. Returns (ids, keys, ndc, hops)."""
+def search(base, graph, entry_ids, q, K, L, metric="l2", trace=False):
+    """Alg. 1 from the navigating node nearest q. Returns (ids, keys, ndc,
+    hops), and with trace=True also the ids of the expanded nodes in the
+    order they were expanded."""
     base = [list(map(float, r)) for r in base]
     q = list(map(float, q))
     ndc = 0
@@ -39,11 +41,13 @@ def search(base, graph, entry_ids, q, K, L, metric="l2"):
     pool = [[best[0], best[1], False]]  # [key, id, checked]
     visited = {best[1]}
     hops = 0
+    order = []
     while True:
         cur = next((c for c in pool if not c[2]), None)
         if cur is None:
             break
         cur[2] = True
+        order.append(cur[1])
         for v in graph[cur[1]]:
             v = int(v)
             if v == SENT:
@@ -58,6 +62,8 @@ def search(base, graph, entry_ids, q, K, L, metric="l2"):
         hops += 1
     ids = [c[1] for c in pool[:K]] + [SENT] * max(0, K - len(pool))
     keys = [c[0] for c in pool[:K]] + [math.inf] * max(0, K - len(pool))
+    if trace:
+        return ids, keys, ndc, hops, order
     return ids, keys, ndc, hops
 
 

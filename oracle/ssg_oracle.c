@@ -376,11 +376,14 @@ int orc_nssg_reverse(const float *base, int64_t n, int d, const uint32_t *G1, in
  * truncates it to L; the loop ends when S holds no unchecked node.
  * forget != 0: a node counts as visited only while it is in S (the result is
  * the same; nodes dropped from S may be computed again).
- * vis: caller-provided n-entry stamp array, tag: this query's stamp. */
+ * vis: caller-provided n-entry stamp array, tag: this query's stamp.
+ * trace (optional): the id of each expanded node in expansion order, the
+ * first trace_cap of them, then SENT. */
 static void search_one(const float *base, int64_t n, int d, const uint32_t *graph, int R,
                        const uint32_t *seeds, int nseeds, const float *q, int K, int L,
                        int metric, int forget, uint32_t *vis, uint32_t tag, cand_t *S,
-                       uint32_t *out_ids, double *out_d, int64_t *ndc_out, int64_t *hops_out) {
+                       uint32_t *out_ids, double *out_d, int64_t *ndc_out, int64_t *hops_out,
+                       uint32_t *trace, int trace_cap) {
     int64_t ndc = 0, hops = 0;
     int sz = 0;
     for (int e = 0; e < nseeds; ++e) {
@@ -399,6 +402,7 @@ static void search_one(const float *base, int64_t n, int d, const uint32_t *grap
         while (i < sz && S[i].checked) ++i;
         if (i == sz) break;
         S[i].checked = 1;
+        if (trace && hops < trace_cap) trace[hops] = S[i].id;
         const uint32_t *row = graph + (size_t)S[i].id * R;
         for (int t = 0; t < R; ++t) {
             uint32_t v = row[t];
@@ -427,6 +431,8 @@ static void search_one(const float *base, int64_t n, int d, const uint32_t *grap
         out_ids[t] = t < sz ? S[t].id : SENT;
         out_d[t] = t < sz ? S[t].dist : INFINITY;
     }
+    if (trace)
+        for (int64_t t = hops; t < trace_cap; ++t) trace[t] = SENT;
     if (ndc_out) *ndc_out = ndc;
     if (hops_out) *hops_out = hops;
 }
@@ -457,12 +463,16 @@ int orc_threads(int n) {
  * navigating node (flags bit 1: seed every navigating node instead).
  * flags bit 0: "forget" visited mode. Per-query L_arr/K_arr override L/K when
  * given (K_arr rows still use a stride of Kmax = K). NDC counts distance
- * evaluations, including the s entry distances; hops counts expansions. */
+ * evaluations, including the s entry distances; hops counts expansions.
+ * out_trace (optional, nq x trace_cap): each query's expanded node ids in
+ * expansion order, padded with SENT. */
 int orc_search(const float *base, int64_t n, int d, const uint32_t *graph, int R,
                const uint32_t *entry, int s, const float *Q, int64_t nq, int K, int L,
                const int32_t *L_arr, const int32_t *K_arr, int metric, int flags,
-               uint32_t *out_ids, double *out_d, int64_t *out_ndc, int64_t *out_hops) {
+               uint32_t *out_ids, double *out_d, int64_t *out_ndc, int64_t *out_hops,
+               uint32_t *out_trace, int trace_cap) {
     if (!base || !graph || !entry || !Q || !out_ids || !out_d) return -1;
+    if (out_trace && trace_cap < 1) return -1;
     if (n < 1 || d < 1 || R < 1 || s < 1 || K < 1 || L < 1 || nq < 0) return -1;
     for (int e = 0; e < s; ++e)
         if (entry[e] >= (uint32_t)n) return -1;
@@ -497,7 +507,8 @@ int orc_search(const float *base, int64_t n, int d, const uint32_t *graph, int R
             }
             search_one(base, n, d, graph, R, seeds, nseeds, q, Kr, Lr, metric, forget, vis,
                        (uint32_t)(r + 1), S, out_ids + (size_t)r * K, out_d + (size_t)r * K,
-                       out_ndc ? out_ndc + r : NULL, out_hops ? out_hops + r : NULL);
+                       out_ndc ? out_ndc + r : NULL, out_hops ? out_hops + r : NULL,
+                       out_trace ? out_trace + (size_t)r * trace_cap : NULL, trace_cap);
             for (int t = Kr; t < K; ++t) {
                 out_ids[(size_t)r * K + t] = SENT;
                 out_d[(size_t)r * K + t] = INFINITY;
@@ -572,7 +583,7 @@ int64_t orc_dfs_connect(const float *base, int64_t n, int d, uint32_t *graph, in
             }
             uint32_t root = roots[e];
             search_one(base, n, d, graph, R, &root, 1, xu, l, l, 0, 0, vis, tag, S, pool_ids,
-                       pool_d, NULL, NULL);
+                       pool_d, NULL, NULL, NULL, 0);
             uint32_t w = SENT;
             for (int t = 0; t < l; ++t) {
                 uint32_t c = pool_ids[t];
