@@ -72,7 +72,9 @@ typedef struct {
                                  FP32 against them and re-sorted before the K
                                  results are written (precision form: search on
                                  BF16/FP8, rerank in FP32); NULL = no rerank */
-    int32_t rerank_k;         /* entries to rerank, 0 = K; capped at L */
+    int32_t rerank_k;         /* pool entries to rerank: max(rerank_k, K) capped
+                                 at L (0 = K), so every returned entry has been
+                                 re-scored */
     int64_t entry_group_size; /* > 0: queries form consecutive groups of this
                                  many, and group g starts from the n_entry ids
                                  entry_ids[g * n_entry ...] (entry_ids then
@@ -88,6 +90,13 @@ typedef struct {
                                  when the ids do not fit). Either form may forget
                                  ids, which costs recomputed distances but never
                                  changes the results. */
+    uint32_t* out_trace;      /* DEVICE uint32 nq x trace_cap, or NULL: the ids of
+                                 the first trace_cap expanded nodes of each query
+                                 in expansion order (Alg. 1 takes the first
+                                 unchecked pool entry each step), then
+                                 SSG_SENTINEL; a debugging record that locates
+                                 where two runs' trajectories part */
+    int32_t trace_cap;        /* entries per trace row (>= 1 with out_trace) */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144
@@ -160,7 +169,8 @@ typedef struct {
     const float* dim_scale;    /* DEVICE float[d] for FP8, else NULL */
     const float* base_f32;     /* DEVICE FP32 vectors for the rerank, or NULL */
     int32_t rerank;            /* 0: none; -1: rerank the first K_i entries of
-                                  each query; > 0: that many (capped at L_i) */
+                                  each query; > 0: max(rerank, K_i) entries
+                                  (capped at L_i) */
     const uint32_t* graph;     /* DEVICE n x R */
     int32_t R;
     const uint32_t* entry_ids; /* DEVICE [n_entry] */
@@ -175,6 +185,9 @@ typedef struct {
     float* out_dists;          /* DEVICE nq x kstride (+inf padding) */
     int32_t* out_ndc;          /* DEVICE int32[nq] or NULL */
     int32_t* out_hops;         /* DEVICE int32[nq] or NULL */
+    uint32_t* out_trace;       /* DEVICE nq x trace_cap expansion record, as in
+                                  ssg_search_opts, or NULL */
+    int32_t trace_cap;
 } ssg_batch_desc;
 
 typedef struct {
@@ -325,6 +338,17 @@ int ssg_merge_shards(const uint32_t* ids, const float* dists, int32_t S, int64_t
 size_t ssg_exact_ssg_workspace_bytes(int64_t n);
 int ssg_exact_ssg(const float* base, int64_t n, int32_t d, double cos2a, int32_t cap, uint32_t* out,
                   int32_t* deg, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * ssg_query_lds_bytes -- on-chip (LDS) bytes one search of pool size L holds
+ * while it runs, in the default launch shape of the batched form (the pool
+ * capacity of L's bucket, the visited set of hash_log2 (0 = default), the
+ * merge stage and, with rerank != 0, room for the rerank keys). Host only, no
+ * device work; returns 0 for arguments the search would reject. Serving uses
+ * it to admit queries against the device's LDS budget.
+ */
+size_t ssg_query_lds_bytes(int32_t L, int32_t R, int32_t d, int32_t dtype, int64_t n, int32_t rerank,
+                           int32_t hash_log2);
 
 /* Workspace bytes ssg_search needs (0: it keeps all search state on chip). */
 size_t ssg_search_workspace_bytes(int64_t n, int64_t nq, int32_t L, int32_t R, int32_t dtype);

@@ -107,12 +107,13 @@ def fp8_dequantize(codes: np.ndarray, s: np.ndarray) -> np.ndarray:
 def search_precision(base_f32, deq, graph, entry_ids, Q, K: int, L: int, metric: str = "l2",
                      rerank: int = 0):
     """Alg. 1 on the dequantized vectors ``deq`` (FP64 keys), then the first
-    min(rerank, |S|) pool entries re-scored with exact FP64 keys against the
-    FP32 vectors and re-sorted by (dist, id); the first K are returned.
-    rerank = 0 means K; without rerank (rerank < 0) the pool order is kept."""
+    min(max(rerank, K), |S|) pool entries re-scored with exact FP64 keys
+    against the FP32 vectors and re-sorted by (dist, id); the first K are
+    returned, so every returned entry has been re-scored. rerank = 0 means K;
+    without rerank (rerank < 0) the pool order is kept."""
     if rerank < 0:
         return core.search(deq, graph, entry_ids, Q, K, L, metric)[:2]
-    rr = min(rerank or K, L)
+    rr = min(max(rerank, K), L)
     Kp = max(K, rr)
     ids, _, _, _ = core.search(deq, graph, entry_ids, Q, Kp, L, metric)
     keys = core.pair_keys(base_f32, Q, ids[:, :rr], metric)

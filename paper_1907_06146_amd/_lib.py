@@ -27,7 +27,8 @@ EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_
            "ssg_search_batched", "ssg_batch_graph_create", "ssg_batch_graph_launch",
            "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
            "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse",
-           "ssg_merge_shards", "ssg_exact_ssg_workspace_bytes", "ssg_exact_ssg")
+           "ssg_merge_shards", "ssg_exact_ssg_workspace_bytes", "ssg_exact_ssg",
+           "ssg_query_lds_bytes")
 
 
 class SSGError(RuntimeError):
@@ -41,7 +42,8 @@ class SearchOpts(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("out_ndc", ctypes.c_void_p),
                 ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
                 ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32),
-                ("entry_group_size", ctypes.c_int64), ("visited_kind", ctypes.c_int32)]
+                ("entry_group_size", ctypes.c_int64), ("visited_kind", ctypes.c_int32),
+                ("out_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -53,7 +55,8 @@ class BatchDesc(ctypes.Structure):
                 ("queries", ctypes.c_void_p), ("nq", ctypes.c_int64), ("L", ctypes.c_void_p),
                 ("K", ctypes.c_void_p), ("kstride", ctypes.c_int32), ("out_ids", ctypes.c_void_p),
                 ("out_dists", ctypes.c_void_p), ("out_ndc", ctypes.c_void_p),
-                ("out_hops", ctypes.c_void_p)]
+                ("out_hops", ctypes.c_void_p), ("out_trace", ctypes.c_void_p),
+                ("trace_cap", ctypes.c_int32)]
 
 
 class Bucket(ctypes.Structure):
@@ -119,6 +122,8 @@ def lib() -> ctypes.CDLL:
             L.ssg_exact_ssg_workspace_bytes.restype = sz
             L.ssg_exact_ssg.argtypes = [P, i64, i32, dbl, i32, P, P, P, sz, P]
             L.ssg_exact_ssg.restype = ctypes.c_int
+            L.ssg_query_lds_bytes.argtypes = [i32, i32, i32, i32, i64, i32, i32]
+            L.ssg_query_lds_bytes.restype = sz
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

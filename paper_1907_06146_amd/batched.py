@@ -51,7 +51,7 @@ class BatchedSearch:
 
     def __init__(self, base, graph, entry_ids, queries, L, K, metric="l2", dim_scale=None,
                  base_f32=None, rerank=0, shapes=None, kstride=None, stats=False, use_graph=True,
-                 bounds=BUCKET_BOUNDS):
+                 bounds=BUCKET_BOUNDS, trace=0):
         _need_cuda("base", base, tuple(_DTYPES))
         _need_cuda("graph", graph, (torch.int32, torch.uint32))
         _need_cuda("entry_ids", entry_ids, (torch.int32, torch.uint32))
@@ -69,6 +69,7 @@ class BatchedSearch:
         self.out_d = torch.empty((self.nq, self.kstride), dtype=torch.float32, device=dev)
         self.ndc = torch.empty(self.nq, dtype=torch.int32, device=dev) if stats else None
         self.hops = torch.empty(self.nq, dtype=torch.int32, device=dev) if stats else None
+        self.trace = torch.empty((self.nq, trace), dtype=torch.int32, device=dev) if trace > 0 else None
         nb = len(self.plan)
         self.ws = torch.empty(_lib.lib().ssg_batch_workspace_bytes(nb) + 256, dtype=torch.uint8,
                               device=dev)
@@ -83,7 +84,8 @@ class BatchedSearch:
             graph.shape[1], entry_ids.data_ptr(), entry_ids.numel(), queries.data_ptr(), self.nq,
             self.L.data_ptr(), self.K.data_ptr(), self.kstride, self.out_ids.data_ptr(),
             self.out_d.data_ptr(), None if self.ndc is None else self.ndc.data_ptr(),
-            None if self.hops is None else self.hops.data_ptr())
+            None if self.hops is None else self.hops.data_ptr(),
+            None if self.trace is None else self.trace.data_ptr(), max(0, int(trace)))
         shapes = shapes or {}
         arr = (_lib.Bucket * nb)()
         for i, ((mL, q), ql) in enumerate(zip(self.plan, self.qlists)):

@@ -37,7 +37,7 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
            waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0,
            base_f32=None, rerank_k: int = 0, out=None, stream=None, entry_group_size: int = 0,
-           visited: str = "auto"):
+           visited: str = "auto", trace: int = 0):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -45,9 +45,12 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
     entry_ids  [s] int32 navigating nodes
     queries    [nq, d] float32
     Returns (ids [nq, K] int32 with -1 padding, dists [nq, K] float32) and,
-    with stats=True, also (ndc [nq] int32, hops [nq] int32).
-    base_f32   optional [n, d] float32: rerank the first rerank_k (0 = K) pool
-               entries exactly in FP32 before writing the K results.
+    with stats=True, also (ndc [nq] int32, hops [nq] int32); with trace = T > 0
+    the last element is the expansion record [nq, T] int32 (ids of the first T
+    expanded nodes in expansion order, -1 after the last).
+    base_f32   optional [n, d] float32: rerank the first max(rerank_k, K)
+               pool entries (capped at L) exactly in FP32 before writing the K
+               results.
     entry_group_size  > 0: entry_ids is [G, s] and queries g*size .. (g+1)*size-1
                start from row g (several shards stored as one block-diagonal
                graph, searched in one launch).
@@ -90,20 +93,21 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
         n_entry = entry_ids.shape[1]
     if visited not in _VISITED:
         raise ValueError(f"visited must be one of {sorted(_VISITED)}, not {visited!r}")
+    tr = torch.empty((nq, trace), dtype=torch.int32, device=dev) if trace > 0 else None
     opts = _lib.SearchOpts(1 if exact_visited else 0, hash_log2, waves_per_block,
                            None if ndc is None else ndc.data_ptr(),
                            None if hops is None else hops.data_ptr(), gather_variant,
                            None if base_f32 is None else base_f32.data_ptr(), rerank_k,
-                           entry_group_size, _VISITED[visited])
+                           entry_group_size, _VISITED[visited],
+                           None if tr is None else tr.data_ptr(), max(0, int(trace)))
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,
         _ptr(graph), graph.shape[1], _ptr(entry_ids), n_entry, _ptr(queries), nq, K, L,
         _METRICS[metric], _ptr(ids), _ptr(dd), ctypes.byref(opts), ctypes.c_void_p(st.cuda_stream))
     _lib.check(rc)
-    if stats:
-        return ids, dd, ndc, hops
-    return ids, dd
+    res = (ids, dd, ndc, hops) if stats else (ids, dd)
+    return res + (tr,) if tr is not None else res
 
 
 def quantize(base_f32, dtype: str, stream=None):

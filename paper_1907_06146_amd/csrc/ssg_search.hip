@@ -253,6 +253,8 @@ struct Args {
   int32_t kstride;        // output row stride (>= every K)
   uint32_t* counter;      // persistent work queue head, or null (one query per wave)
   int64_t entry_group;    // > 0: query i uses entry[(i / entry_group) * s ...]; 0: all share
+  uint32_t* out_trace;    // nq x trace_cap expanded ids in expansion order, or null
+  int32_t trace_cap;
 };
 
 // ------------------------------------------------------------------ kernel
@@ -502,6 +504,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     size = 1;
     p = key_id(best);
     if (lane == 0) visit(p);
+    if (a.out_trace && lane == 0) a.out_trace[(size_t)qid * a.trace_cap] = p;
     hcount = 1;
     wave_sync();
   }
@@ -602,6 +605,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       more = rank_u < L;
     }
     if (more) {
+      // expansion number hops + 1 (0-based: hops) is u
+      if (a.out_trace && lane == 0 && hops < a.trace_cap)
+        a.out_trace[(size_t)qid * a.trace_cap + hops] = key_id(u);
       // stage it now: its gathers overlap the merge below
       const uint32_t nb_next =
           u == u_spec ? nb_spec : lane < R ? a.graph[(size_t)key_id(u) * R + lane] : kSent;
@@ -650,8 +656,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
   // ---- optional rerank: exact FP32 keys of the first `rerank` pool entries
   // against the FP32 vectors, re-sorted by (dist, id). The visited table is
   // dead here, so its LDS holds the new keys; `stage` holds the sorted order.
+  // (never fewer than K entries: every returned entry is re-scored)
   if (a.base_f32 != nullptr) {
-    const int rr = min(a.rerank < 0 ? K : a.rerank, size);
+    const int rr = min(a.rerank < 0 ? K : max(a.rerank, K), size);
     uint32_t* rids = bids;  // reused 64 at a time
     uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
     const int d4 = a.d >> 2;
@@ -720,6 +727,8 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     if (a.out_ndc) a.out_ndc[qid] = ndc;
     if (a.out_hops) a.out_hops[qid] = hops;
   }
+  if (a.out_trace)
+    for (int i = hops + lane; i < a.trace_cap; i += 64) a.out_trace[(size_t)qid * a.trace_cap + i] = kSent;
   wave_sync();  // LDS of this wave is reused by its next query
 }
 
@@ -1079,6 +1088,21 @@ const char* ssg_version(void) { return "libssg 0.1 gfx950"; }
 
 size_t ssg_search_workspace_bytes(int64_t, int64_t, int32_t, int32_t, int32_t) { return 0; }
 
+size_t ssg_query_lds_bytes(int32_t L, int32_t R, int32_t d, int32_t dtype, int64_t n, int32_t rerank,
+                           int32_t hash_log2) {
+  if (L < 1 || L > SSG_L_MAX || R < 1 || R > SSG_R_MAX || d < 1 || n < 1) return 0;
+  if (dtype != SSG_F32 && dtype != SSG_BF16 && dtype != SSG_FP8E4M3) return 0;
+  const int epc = dtype == SSG_F32 ? 4 : dtype == SSG_BF16 ? 8 : 16;
+  if (d % epc) return 0;
+  const int preg = preg_for(L);
+  const Launch lc = pick_launch(dtype, d / epc, preg, 0, true);
+  VisitedPlan vp;
+  const std::string keep = g_err;  // a size query leaves the error message alone
+  const int rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, 0, n, rerank != 0, hash_log2, &vp);
+  g_err = keep;
+  return rc ? 0 : vp.per_wave;
+}
+
 int ssg_validate_graph(const uint32_t* graph, int64_t n, int32_t R) {
   if (!graph || n < 1 || R < 1) return fail(SSG_EINVAL, "bad graph arguments");
   std::string seen;
@@ -1145,13 +1169,17 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
   a.counter = nullptr;
   if (o.entry_group_size < 0) return fail(SSG_EINVAL, "entry_group_size must be >= 0");
   a.entry_group = o.entry_group_size;
+  if (o.trace_cap < 0 || (o.out_trace && o.trace_cap < 1))
+    return fail(SSG_EINVAL, "out_trace needs trace_cap >= 1");
+  a.out_trace = o.trace_cap > 0 ? o.out_trace : nullptr;
+  a.trace_cap = o.trace_cap;
   a.base_f32 = o.base_f32;
   a.rerank = 0;
   if (o.base_f32) {
     if (reinterpret_cast<uintptr_t>(o.base_f32) % 16)
       return fail(SSG_EINVAL, "base_f32 must be 16-byte aligned");
     if (o.rerank_k < 0) return fail(SSG_EINVAL, "rerank_k must be >= 0");
-    a.rerank = std::min(o.rerank_k > 0 ? o.rerank_k : K, L);
+    a.rerank = std::min(std::max(o.rerank_k, K), L);
   }
   VisitedPlan vp;
   rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, o.exact_visited ? 3 : o.visited_kind, n,
@@ -1258,6 +1286,8 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
   if (D->rerank != 0 && !D->base_f32) return fail(SSG_EINVAL, "rerank needs base_f32");
   if (D->base_f32 && reinterpret_cast<uintptr_t>(D->base_f32) % 16)
     return fail(SSG_EINVAL, "base_f32 must be 16-byte aligned");
+  if (D->trace_cap < 0 || (D->out_trace && D->trace_cap < 1))
+    return fail(SSG_EINVAL, "out_trace needs trace_cap >= 1");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1314,6 +1344,8 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     a.L_arr = D->L;
     a.K_arr = D->K;
     a.kstride = D->kstride;
+    a.out_trace = D->trace_cap > 0 ? D->out_trace : nullptr;
+    a.trace_cap = D->trace_cap;
     bl.counter = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(ws) + (size_t)i * 256);
     a.counter = bl.counter;
     bl.fn = lc.fn;

@@ -14,11 +14,22 @@ Two ways to put requests on the device:
 * ``Scheduler`` + ``GpuDevice``: one launch per request, requests overlap on
   per-slot streams;
 * ``BatchScheduler`` + ``GpuBatchDevice`` (continuous batching): whenever a
-  batch slot is free, every waiting request (FIFO, up to a query budget) is
-  launched together as one mixed batch through the persistent batched kernel,
-  each query with its own request's pool size L and result count K. This
-  keeps the device full with a few launches at a time instead of one launch
-  per request.
+  batch slot is free, the waiting requests that fit the device budget (FIFO)
+  are launched together as one mixed batch through the persistent batched
+  kernel, each query with its own request's pool size L and result count K.
+  This keeps the device full with a few launches at a time instead of one
+  launch per request.
+
+Admission budget (``DeviceBudget``): a query in flight holds on-chip state
+(LDS: its pool, merge stage and visited set, sized by its L bucket; the
+library reports the bytes) and HBM staging (its query row, L and K, and its
+K output rows). A batch is admitted only while the in-flight totals stay
+within the budget: the LDS budget is the bytes of the searches the GPU holds
+at once, times an oversubscription factor (queued waves start as soon as
+resident ones finish); the HBM budget is the staging and output memory the
+device preallocated. A request that can never fit (more queries or a larger
+K than a slot holds, or more bytes than the whole budget) is finished at once
+with an error instead of stalling the queue.
 
 The schedulers are independent of the device: the GPU devices launch through
 the library, the fake devices (tests) complete work after scripted times.
@@ -48,6 +59,7 @@ class Request:
     slot: int = -1
     ids: np.ndarray | None = None
     dists: np.ndarray | None = None
+    error: str | None = None
 
     @property
     def latency(self) -> float:
@@ -71,6 +83,12 @@ class Scheduler:
         self.max_running_seen = 0
 
     def submit(self, r: Request):
+        cap = getattr(self.dev, "max_queries", None)
+        kmax = getattr(self.dev, "max_K", None)
+        if (cap is not None and len(r.queries) > cap) or (kmax is not None and r.K > kmax):
+            _reject(r, f"request of {len(r.queries)} queries with K = {r.K} exceeds a slot "
+                       f"({cap} queries, K <= {kmax})", self.done)
+            return
         self.waiting.append(r)
 
     def _fits(self, r: Request) -> bool:
@@ -107,26 +125,80 @@ class Scheduler:
         return not self.running and not self.waiting
 
 
+def _reject(r: Request, msg: str, done: list):
+    r.error = msg
+    r.admitted = r.finished = r.arrival
+    done.append(r)
+
+
+class DeviceBudget:
+    """Byte budget for the queries in flight on one device.
+
+    lds_bytes:  on-chip bytes the in-flight searches may hold together
+    hbm_bytes:  staging + output bytes they may hold together
+    lds_of:     L -> LDS bytes of one search of pool size L
+    hbm_of:     K -> HBM bytes of one query with K results
+    """
+
+    def __init__(self, lds_bytes: int, hbm_bytes: int, lds_of, hbm_of):
+        if lds_bytes < 1 or hbm_bytes < 1:
+            raise ValueError("budgets must be positive")
+        self.lds_bytes, self.hbm_bytes = int(lds_bytes), int(hbm_bytes)
+        self.lds_of, self.hbm_of = lds_of, hbm_of
+
+    def cost(self, r: Request) -> tuple[int, int]:
+        b = len(r.queries)
+        return b * int(self.lds_of(r.L)), b * int(self.hbm_of(r.K))
+
+
 class BatchScheduler:
     """Continuous batching: whenever one of ``n_slots`` batch slots is free,
     the waiting requests are taken in arrival order while their queries fit
-    ``max_batch`` (a larger request goes alone) and launched as one batch."""
+    ``max_batch`` and the bytes of everything in flight fit ``budget`` (a
+    ``DeviceBudget``; None = queries alone), and launched as one batch. A
+    request waits while the budget is taken (FIFO: later requests wait behind
+    it) and is rejected if it could never fit."""
 
-    def __init__(self, device, n_slots: int, max_batch: int):
+    def __init__(self, device, n_slots: int, max_batch: int, budget: DeviceBudget | None = None):
         if n_slots < 1 or max_batch < 1:
             raise ValueError("need at least one slot and a positive batch size")
         self.dev = device
         self.free = list(range(n_slots))[::-1]
-        self.max_batch = max_batch
+        cap = getattr(device, "max_queries", None)
+        self.max_batch = min(max_batch, cap) if cap else max_batch
+        self.max_K = getattr(device, "max_K", None)
+        self.budget = budget
+        self.inflight = [0, 0]  # LDS, HBM bytes of admitted, unfinished batches
+        self.batch_cost: dict[int, tuple[int, int]] = {}
         self.running: dict[int, list[Request]] = {}
         self.waiting: collections.deque[Request] = collections.deque()
         self.done: list[Request] = []
         self.batches = 0
         self.max_running_seen = 0
         self.max_batch_seen = 0
+        self.max_inflight_seen = [0, 0]
+        self.budget_waits = 0  # steps where a free slot idled because the budget was taken
 
     def submit(self, r: Request):
+        if len(r.queries) > self.max_batch or (self.max_K is not None and r.K > self.max_K):
+            _reject(r, f"request of {len(r.queries)} queries with K = {r.K} exceeds a batch "
+                       f"({self.max_batch} queries, K <= {self.max_K})", self.done)
+            return
+        if self.budget is not None:
+            c = self.budget.cost(r)
+            if c[0] > self.budget.lds_bytes or c[1] > self.budget.hbm_bytes:
+                _reject(r, f"request needs {c[0]} LDS / {c[1]} HBM bytes, over the whole budget "
+                           f"({self.budget.lds_bytes} / {self.budget.hbm_bytes})", self.done)
+                return
         self.waiting.append(r)
+
+    def _cost(self, r: Request) -> tuple[int, int]:
+        return self.budget.cost(r) if self.budget is not None else (0, 0)
+
+    def _fits(self, used, c) -> bool:
+        if self.budget is None:
+            return True
+        return used[0] + c[0] <= self.budget.lds_bytes and used[1] + c[1] <= self.budget.hbm_bytes
 
     def step(self, now: float) -> int:
         changes = 0
@@ -138,18 +210,33 @@ class BatchScheduler:
                     r.ids, r.dists, r.finished = ids, dd, t
                     self.done.append(r)
                 del self.running[slot]
+                c = self.batch_cost.pop(slot)
+                self.inflight = [self.inflight[0] - c[0], self.inflight[1] - c[1]]
                 self.free.append(slot)
                 changes += 1
         while self.waiting and self.free:
+            used = list(self.inflight)
+            c = self._cost(self.waiting[0])
+            if not self._fits(used, c):
+                self.budget_waits += 1
+                break  # the head waits for bytes to free up; FIFO keeps the rest behind it
             batch = [self.waiting.popleft()]
+            used = [used[0] + c[0], used[1] + c[1]]
             total = len(batch[0].queries)
             while self.waiting and total + len(self.waiting[0].queries) <= self.max_batch:
+                c = self._cost(self.waiting[0])
+                if not self._fits(used, c):
+                    break
                 r = self.waiting.popleft()
                 batch.append(r)
+                used = [used[0] + c[0], used[1] + c[1]]
                 total += len(r.queries)
             slot = self.free.pop()
             for r in batch:
                 r.slot, r.admitted = slot, now
+            self.batch_cost[slot] = (used[0] - self.inflight[0], used[1] - self.inflight[1])
+            self.inflight = used
+            self.max_inflight_seen = [max(a, b) for a, b in zip(self.max_inflight_seen, used)]
             self.running[slot] = batch
             self.batches += 1
             self.max_running_seen = max(self.max_running_seen, len(self.running))
@@ -195,10 +282,12 @@ def poisson_requests(rng, n_req: int, rate: float, pool_q: np.ndarray, L_choices
 
 
 def summarize(done: list[Request]) -> dict:
-    lat = np.array([r.latency for r in done])
-    nq = sum(len(r.queries) for r in done)
-    span = max(r.finished for r in done) - min(r.arrival for r in done)
-    return {"requests": len(done), "queries": int(nq), "makespan_s": span, "qps": nq / span,
+    ok = [r for r in done if r.error is None]
+    lat = np.array([r.latency for r in ok])
+    nq = sum(len(r.queries) for r in ok)
+    span = max(r.finished for r in ok) - min(r.arrival for r in ok)
+    return {"requests": len(ok), "rejected": len(done) - len(ok), "queries": int(nq),
+            "makespan_s": span, "qps": nq / span,
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3)}
@@ -260,6 +349,7 @@ class GpuDevice:
         self.torch, self.search = torch, search
         self.index = (base, graph, entry_ids)
         self.metric, self.dim_scale, self.base_f32, self.rerank = metric, dim_scale, base_f32, rerank
+        self.max_queries, self.max_K = max_batch, max_K
         dev = base.device
         d = base.shape[1]
         self.slots = []
@@ -323,6 +413,7 @@ class GpuBatchDevice:
         self.dtype, self.metric = _DTYPES[base.dtype], _METRICS[metric]
         self.rerank = -1 if rerank else 0
         self.max_K, self.shapes = max_K, shapes or {}
+        self.max_queries, self.n_slots = max_batch, n_slots
         dev = base.device
         d = base.shape[1]
         nbmax = len(BUCKET_BOUNDS)
@@ -397,6 +488,32 @@ class GpuBatchDevice:
 
     def poll(self, slot):
         return self.slots[slot]["ev"].query()
+
+    def budget(self, oversubscribe: float = 2.0) -> DeviceBudget:
+        """The device's byte budget: LDS = compute units x LDS per unit x
+        ``oversubscribe`` (searches beyond what the chip holds at once wait
+        on the device for a resident one to finish); HBM = the staging and
+        output buffers of every slot. Per query: the library's LDS bytes for
+        its L, and d * 4 + 12 + K * 8 bytes of staging and output."""
+        torch, _lib = self.torch, self.lib_mod
+        base, graph = self.index[0], self.index[1]
+        props = torch.cuda.get_device_properties(base.device)
+        per_cu = getattr(props, "shared_memory_per_multiprocessor", 0) or 160 * 1024
+        n, d = base.shape
+        R = graph.shape[1]
+        memo = {}
+
+        def lds_of(L):
+            if L not in memo:
+                memo[L] = int(_lib.lib().ssg_query_lds_bytes(L, R, d, self.dtype, n, self.rerank, 0))
+                if memo[L] == 0:
+                    raise ValueError(f"no search of pool size {L} fits this index")
+            return memo[L]
+
+        def hbm_of(K):
+            return d * 4 + 12 + K * 8
+        return DeviceBudget(int(props.multi_processor_count * per_cu * oversubscribe),
+                            self.n_slots * self.max_queries * hbm_of(self.max_K), lds_of, hbm_of)
 
     def results(self, slot, reqs):
         s = self.slots[slot]

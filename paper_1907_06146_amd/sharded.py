@@ -9,8 +9,10 @@ at an offset, its graph's ids shifted by it) and all S x nq searches run in
 one launch, each query group starting from its own shard's navigating nodes
 (``entry_group_size``); a graph edge never leaves its shard, so each search
 stays inside its shard. ``combined=False`` instead launches one ordinary
-search per shard on S streams. Either way everything a single index supports
-(storage precision, rerank, launch shape) applies per shard.
+search per shard on S streams. Either way the shards may be stored in FP32 or
+BF16 and the launch-shape options apply to every shard. Arguments that belong
+to one index's vectors (an FP8 per-dimension scale, FP32 rerank vectors) are
+rejected: a single value cannot describe S shards.
 """
 
 from __future__ import annotations
@@ -75,6 +77,11 @@ class ShardedIndex:
         """Search every shard with pool size L, keep K per shard, merge to
         K_out (default K) by (distance, global id). Returns (ids, dists)."""
         K_out = K_out or K
+        for k in ("dim_scale", "base_f32", "rerank_k"):
+            v = kw.get(k)
+            if v is not None and not (isinstance(v, int) and v == 0):
+                raise ValueError(f"{k} describes one index's vectors and cannot be applied to "
+                                 f"{self.S} shards")
         nq = queries.shape[0]
         dev = queries.device
         main = torch.cuda.current_stream(dev)

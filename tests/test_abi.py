@@ -171,3 +171,28 @@ def _call_ex(n=100, **opts):
 def test_search_options_rejected_on_host(n, opts, code):
     assert _call_ex(n, **opts) == code
     assert len(_lib.last_error()) > 0
+
+
+def test_query_lds_bytes_on_host():
+    """The per-search LDS figure serving admits by: grows with the pool's
+    bucket, is 0 for shapes the search rejects, and leaves the last error
+    message alone."""
+    L = _lib.lib()
+    f = L.ssg_query_lds_bytes
+    b64 = f(64, 50, 128, _lib.SSG_F32, 1_000_000, 0, 0)
+    b128 = f(100, 50, 128, _lib.SSG_F32, 1_000_000, 0, 0)
+    b512 = f(512, 50, 128, _lib.SSG_F32, 1_000_000, 0, 0)
+    assert 0 < b64 < b128 < b512 <= 64 * 1024
+    assert f(33, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 0) == b64  # one bucket, one size
+    assert b64 % 16 == 0
+    # a 4096-entry 16-bit tag cache (8 KB) and the merge stage are in it
+    assert b64 >= 8192 + 64 * 8
+    assert f(513, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 0) == 0
+    assert f(64, 65, 128, _lib.SSG_F32, 10 ** 6, 0, 0) == 0
+    assert f(64, 50, 100, _lib.SSG_BF16, 10 ** 6, 0, 0) == 0  # d not a multiple of 8
+    assert f(64, 50, 128, 7, 10 ** 6, 0, 0) == 0
+    assert L.ssg_validate_graph(None, 1, 1) == _lib.SSG_EINVAL
+    msg = _lib.last_error()
+    f(64, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 99)  # a bad visited size: 0, message kept
+    assert f(64, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 99) == 0
+    assert _lib.last_error() == msg

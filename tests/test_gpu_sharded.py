@@ -62,6 +62,19 @@ def test_sharded_search_matches_oracle(S, combined):
         # integer data: FP32 distances are exact, so the merge must agree exactly
         assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
         assert np.array_equal(gd.cpu().numpy().astype(np.float64), od)
+    # BF16 shards hold these integers exactly: the same results
+    idx16 = ShardedIndex([_dev(b).to(torch.bfloat16) for b in bases], [_dev(g) for g in graphs],
+                         [_dev(e) for e in entries], parts, combined=combined)
+    gi16, gd16 = idx16.search(_dev(q), 10, 40, 10)
+    torch.cuda.synchronize()
+    oi, od = _oracle_sharded(parts, bases, graphs, entries, q, 10, 40, 10)
+    assert np.array_equal(gi16.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gd16.cpu().numpy().astype(np.float64), od)
+    # one index's rerank vectors or FP8 scale cannot describe S shards
+    for kw in (dict(base_f32=_dev(bases[0])), dict(dim_scale=_dev(np.ones(128, np.float32))),
+               dict(rerank_k=5)):
+        with pytest.raises(ValueError):
+            idx.search(_dev(q), 10, 40, **kw)
 
 
 def test_merge_ties_and_padding():
