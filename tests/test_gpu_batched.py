@@ -62,7 +62,7 @@ def test_mixed_batch_matches_oracle(c4s):
     otr = _oracle_trace(base, g, entry, q, Lq, Kq, "ip")
     rows = classify(base, q, gi, oi, "ip", 1e-5, gtr, otr)
     print(f"c4s mixed batch: {rows.summary()}", flush=True)
-    assert_parity(rows, 0.999, "c4s mixed batch")
+    assert_parity(rows, 0.99, "c4s mixed batch")
     assert_hops_explained(base, q, rows.exact, bs.hops.cpu().numpy(), ohops, gtr, otr, "ip")
     for r in range(len(q)):  # padding past each K_i
         assert (gi[r, Kq[r]:] == SENT).all() and np.isinf(dd.cpu().numpy()[r, Kq[r]:]).all()

@@ -153,8 +153,9 @@ def test_c1_pool_sizes_and_large_k(c1_graph, L):
     oi, od, _, _ = core.search(base, g, entry, q, K, L)
     gi, gd, _, _, gt_ = _gpu(base, g, entry, q, K, L, trace=_trace_cap(L))
     # lists up to 512 long on float data: near-equal keys deep in the list may
-    # swap between FP32 and FP64; every differing row must be explained
-    _compare(base, g, entry, q, K, L, gi, gd, oi, od, gt_, min_exact=0.99)
+    # swap between FP32 and FP64 (at L = 512 about one row in 25 holds such a
+    # pair); every differing row must be explained
+    _compare(base, g, entry, q, K, L, gi, gd, oi, od, gt_, min_exact=0.99 if L <= 50 else 0.95)
     assert (gi[:, L:] == SENT).all() and np.isinf(gd[:, L:]).all()
 
 
