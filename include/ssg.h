@@ -97,6 +97,11 @@ typedef struct {
                                  SSG_SENTINEL; a debugging record that locates
                                  where two runs' trajectories part */
     int32_t trace_cap;        /* entries per trace row (>= 1 with out_trace) */
+    int32_t queries_per_wave; /* searches sharing one 64-lane wavefront: 1 (64
+                                 lanes per query), 2 (32 lanes each; needs
+                                 L <= 256, the tag-cache visited set and a
+                                 compiled dimension: 96 or 128), or 0 = the
+                                 library's choice. Results are the same. */
 } ssg_search_opts;
 
 #define SSG_EXACT_VISITED_MAX_N 262144
@@ -201,6 +206,8 @@ typedef struct {
     int32_t blocks;            /* persistent grid size; 0 = fill the GPU once */
     int32_t visited_kind;      /* visited-set form, as ssg_search_opts.visited_kind
                                   (0 default, 1 hash, 2 tag cache) */
+    int32_t queries_per_wave;  /* as ssg_search_opts.queries_per_wave (bucket
+                                  max_L <= 256 for 2) */
 } ssg_bucket;
 
 /* Workspace for nb buckets (one work-queue counter each). */

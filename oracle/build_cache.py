@@ -9,7 +9,10 @@ Steps (all FP64 oracle code, no GPU):
      checking, DFS spanning from the navigating nodes;
   4. exact ground truth of the queries (Eq. 1's G);
   5. Alg. 1 from the nearest navigating node at the workload's pool sizes,
-     recording ids, keys, NDC and hops as the stored expected values.
+     recording ids, keys, NDC and hops as the stored expected values;
+  6. for workloads with a steady-state query set (``nq_steady``): its exact
+     top 10 and Alg. 1's first 10 ids, NDC and hops at the operating pool
+     size.
 The kNN graph is kept under data/_cpu/ (not needed by GPU runs).
 """
 
@@ -35,6 +38,7 @@ def log(*a):
 
 def build(name: str, sweep: bool, expand: str, sweep_only: bool = False):
     cfg = synth.CONFIGS[name]
+    core.lib()  # load the C oracle now: a rebuild during a long run cannot mix versions
     t0 = time.time()
     base = synth.base_vectors(cfg)
     q = synth.queries(cfg, base)
@@ -105,9 +109,29 @@ def build(name: str, sweep: bool, expand: str, sweep_only: bool = False):
         cache.save(name, {"oracle_mixed_ids": ids, "oracle_mixed_d": dd, "oracle_mixed_ndc": ndc,
                           "oracle_mixed_hops": hops}, {})
     op = [r["L"] for r in rows if r["recall10"] is not None and r["recall10"] >= 0.95]
-    with open(os.path.join(cache.path(name), "sweep.json"), "w") as f:
-        json.dump(dict(rows=rows, L_op=op[0] if op else None), f, indent=1)
-    log(name, "done", f"{time.time() - t0:.1f}s", "L_op", op[0] if op else None)
+    L_op = op[0] if op else cfg["L"]
+    if sweep:
+        with open(os.path.join(cache.path(name), "sweep.json"), "w") as f:
+            json.dump(dict(rows=rows, L_op=op[0] if op else None), f, indent=1)
+    if cfg.get("nq_steady"):
+        steady(name, cfg, base, g, entry, L_op)
+    log(name, "done", f"{time.time() - t0:.1f}s", "L_op", L_op)
+
+
+def steady(name, cfg, base, g, entry, L):
+    """Steady-state query set: exact top 10 and the oracle at pool size L."""
+    t = time.time()
+    qs = synth.steady_queries(cfg)
+    gi, _ = core.ground_truth(base, qs, 10, cfg["metric"], verbose=True)
+    log("steady ground truth", qs.shape, f"{time.time() - t:.1f}s")
+    t = time.time()
+    ids, _, ndc, hops = core.search(base, g, entry, qs, cfg["K"], L, cfg["metric"])
+    r10 = core.recall_at(ids, gi, 10)
+    log("steady oracle", f"L={L}", f"{time.time() - t:.1f}s", "recall@10", r10)
+    cache.save(name, {"steady_gt_ids": gi, f"steady_L{L}_ids10": np.ascontiguousarray(ids[:, :10]),
+                      f"steady_L{L}_ndc": ndc.astype(np.int32), f"steady_L{L}_hops": hops.astype(np.int32)},
+               {"steady": dict(nq=int(len(qs)), L=int(L), recall10=r10, queries_sha=synth.checksum(qs),
+                               ndc=float(ndc.mean()), hops=float(hops.mean()))})
 
 
 def main():

@@ -43,7 +43,8 @@ class SearchOpts(ctypes.Structure):
                 ("out_hops", ctypes.c_void_p), ("gather_variant", ctypes.c_int32),
                 ("base_f32", ctypes.c_void_p), ("rerank_k", ctypes.c_int32),
                 ("entry_group_size", ctypes.c_int64), ("visited_kind", ctypes.c_int32),
-                ("out_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
+                ("out_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32),
+                ("queries_per_wave", ctypes.c_int32)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -63,7 +64,7 @@ class Bucket(ctypes.Structure):
     _fields_ = [("qlist", ctypes.c_void_p), ("count", ctypes.c_int64), ("max_L", ctypes.c_int32),
                 ("gather_variant", ctypes.c_int32), ("hash_log2", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("visited_kind", ctypes.c_int32)]
+                ("visited_kind", ctypes.c_int32), ("queries_per_wave", ctypes.c_int32)]
 
 
 _lock = threading.Lock()

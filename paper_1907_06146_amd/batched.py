@@ -45,8 +45,9 @@ class BatchedSearch:
     base / base_f32 / dim_scale as in ``search``; L, K: int32 [nq] (host or
     device); rerank: 0 none, -1 the first K_i entries, > 0 a fixed count.
     shapes: {max_L bucket capacity: dict(gather_variant, hash_log2,
-    waves_per_block, blocks, visited)} from the autotuner (visited: "auto",
-    "hash" or "cache", the form of the LDS visited set).
+    waves_per_block, blocks, visited, queries_per_wave)} from the autotuner
+    (visited: "auto", "hash" or "cache", the form of the LDS visited set;
+    queries_per_wave: searches per wavefront, 0 = the library's choice).
     """
 
     def __init__(self, base, graph, entry_ids, queries, L, K, metric="l2", dim_scale=None,
@@ -93,7 +94,8 @@ class BatchedSearch:
             sh = shapes.get(cap, {})
             arr[i] = _lib.Bucket(ql.data_ptr(), len(q), mL, sh.get("gather_variant", 0),
                                  sh.get("hash_log2", 0), sh.get("waves_per_block", 0),
-                                 sh.get("blocks", 0), _VISITED[sh.get("visited", "auto")])
+                                 sh.get("blocks", 0), _VISITED[sh.get("visited", "auto")],
+                                 sh.get("queries_per_wave", 0))
         self.buckets = arr
         self.graph = None
         if use_graph:

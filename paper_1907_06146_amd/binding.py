@@ -37,7 +37,7 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
            dim_scale=None, exact_visited: bool = False, stats: bool = False,
            waves_per_block: int = 0, hash_log2: int = 0, gather_variant: int = 0,
            base_f32=None, rerank_k: int = 0, out=None, stream=None, entry_group_size: int = 0,
-           visited: str = "auto", trace: int = 0):
+           visited: str = "auto", trace: int = 0, queries_per_wave: int = 0):
     """Alg. 1 from the nearest navigating node for every row of ``queries``.
 
     base       [n, d] float32 | bfloat16 | uint8 (FP8 E4M3 codes, with dim_scale)
@@ -56,6 +56,9 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
                graph, searched in one launch).
     visited    "auto" | "hash" | "cache": form of the LDS visited set (ignored
                with exact_visited); every form gives the same results.
+    queries_per_wave  1: one search per 64-lane wavefront; 2: two searches of
+               32 lanes each (L <= 256, tag-cache visited set, d = 96 or 128);
+               0: the library's choice. Same results either way.
     """
     _need_cuda("base", base, tuple(_DTYPES))
     _need_cuda("graph", graph, (torch.int32, torch.uint32))
@@ -99,7 +102,8 @@ def search(base, graph, entry_ids, queries, K: int, L: int, metric: str = "l2",
                            None if hops is None else hops.data_ptr(), gather_variant,
                            None if base_f32 is None else base_f32.data_ptr(), rerank_k,
                            entry_group_size, _VISITED[visited],
-                           None if tr is None else tr.data_ptr(), max(0, int(trace)))
+                           None if tr is None else tr.data_ptr(), max(0, int(trace)),
+                           int(queries_per_wave))
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     rc = _lib.lib().ssg_search_ex(
         _ptr(base), n, d, dtype, _ptr(dim_scale) if dtype == _lib.SSG_FP8E4M3 else None,

@@ -56,206 +56,9 @@
 
 #include "ssg.h"
 #include "ssg_internal.h"
+#include "ssg_search_common.h"
 
 namespace {
-
-constexpr uint32_t kSent = 0xFFFFFFFFu;
-constexpr uint64_t kNoKey = ~0ull;
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Monotone map of a float to uint32 (negative zero folded onto positive zero).
-__device__ __forceinline__ uint32_t ord_f32(float f) {
-  uint32_t b = __float_as_uint(f);
-  if (b == 0x80000000u) b = 0u;
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float unord_f32(uint32_t o) {
-  uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
-  return __uint_as_float(b);
-}
-__device__ __forceinline__ uint64_t make_key(float dist, uint32_t id) {
-  return ((uint64_t)ord_f32(dist) << 32) | ((uint64_t)id << 1);
-}
-__device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)(k >> 1) & 0x7FFFFFFFu; }
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
-  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  uint32_t lo = __shfl_xor((int)(uint32_t)v, m, 64);
-  uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
-// x + the value of lane ^ OFF. Within a row of 16 lanes the partner comes
-// from a DPP lane move (VALU; row_shr:n reads lane i - n, row_shl:n lane
-// i + n, quad_perm permutes each quad), across rows from a lane shuffle.
-// Call with every lane active.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int OFF>
-__device__ __forceinline__ float add_xor_lane(float x, int lane) {
-  if constexpr (OFF == 1) return x + dpp_f32<0xB1>(x);  // quad_perm [1,0,3,2]
-  if constexpr (OFF == 2) return x + dpp_f32<0x4E>(x);  // quad_perm [2,3,0,1]
-  if constexpr (OFF == 4 || OFF == 8) {
-    const float lo = dpp_f32<0x110 + OFF>(x);  // row_shr: lane - OFF
-    const float hi = dpp_f32<0x100 + OFF>(x);  // row_shl: lane + OFF
-    return x + ((lane & OFF) ? lo : hi);
-  }
-  if constexpr (OFF >= 16) return x + __shfl_xor(x, OFF, 64);
-}
-// Sum over each aligned group of G lanes, on every lane of the group; the
-// same additions in the same order as a butterfly of lane shuffles from
-// offset G/2 down to 1.
-template <int G>
-__device__ __forceinline__ float group_sum(float x, int lane) {
-  if constexpr (G >= 64) x = add_xor_lane<32>(x, lane);
-  if constexpr (G >= 32) x = add_xor_lane<16>(x, lane);
-  if constexpr (G >= 16) x = add_xor_lane<8>(x, lane);
-  if constexpr (G >= 8) x = add_xor_lane<4>(x, lane);
-  if constexpr (G >= 4) x = add_xor_lane<2>(x, lane);
-  if constexpr (G >= 2) x = add_xor_lane<1>(x, lane);
-  return x;
-}
-
-// Minimum of a 64-bit value over the wavefront, read back on every lane.
-// Row-local DPP shifts (VALU latency, not the LDS pipe of lane shuffles)
-// reduce each row of 16 into its lane 15; row broadcasts fold the four rows
-// into lane 63.
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_min64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_update_dpp(0xFFFFFFFFu, (uint32_t)v, CTRL, 0xF, 0xF, false);
-  const uint32_t hi = __builtin_amdgcn_update_dpp(0xFFFFFFFFu, (uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
-  const uint64_t o = ((uint64_t)hi << 32) | lo;
-  return o < v ? o : v;
-}
-__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
-  v = dpp_min64<0x111>(v);  // row_shr:1
-  v = dpp_min64<0x112>(v);  // row_shr:2
-  v = dpp_min64<0x114>(v);  // row_shr:4
-  v = dpp_min64<0x118>(v);  // row_shr:8
-  v = dpp_min64<0x142>(v);  // row_bcast:15
-  v = dpp_min64<0x143>(v);  // row_bcast:31
-  return readlane64(v, 63);
-}
-
-__device__ __forceinline__ int lane_prefix(uint64_t mask) {  // set bits below this lane
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-__device__ __forceinline__ uint32_t hash_slot(uint32_t id, uint32_t mask) {
-  return (id * 0x9E3779B1u) >> 7 & mask;
-}
-
-// ------------------------------------------------------------------ vector types
-// A "chunk" is 16 bytes of a stored vector: 4 f32, 8 bf16 or 16 fp8 values.
-struct F32T {
-  static constexpr int kEpc = 4;
-  static constexpr bool kScaled = false;
-  __device__ static __forceinline__ void decode(uint4 c, float* x) {
-    x[0] = __uint_as_float(c.x);
-    x[1] = __uint_as_float(c.y);
-    x[2] = __uint_as_float(c.z);
-    x[3] = __uint_as_float(c.w);
-  }
-};
-struct BF16T {
-  static constexpr int kEpc = 8;
-  static constexpr bool kScaled = false;
-  __device__ static __forceinline__ void decode(uint4 c, float* x) {
-    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      x[2 * i] = __uint_as_float(w[i] << 16);
-      x[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
-    }
-  }
-};
-// OCP FP8 E4M3 (bias 7, no infinities, S.1111.111 is NaN): exact decode by
-// bit placement for normal codes and by one multiply for subnormal codes.
-struct FP8T {
-  static constexpr int kEpc = 16;
-  static constexpr bool kScaled = true;
-  __device__ static __forceinline__ float one(uint32_t b) {
-    uint32_t s = (b & 0x80u) << 24;
-    uint32_t e = (b >> 3) & 0xFu;
-    uint32_t m = b & 0x7u;
-    float v = (e == 0u) ? (float)m * 0.001953125f  // m * 2^-9
-                        : __uint_as_float(((e + 120u) << 23) | (m << 20));
-    return __uint_as_float(__float_as_uint(v) | s);
-  }
-  __device__ static __forceinline__ void decode(uint4 c, float* x) {
-    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) x[4 * i + b] = one((w[i] >> (8 * b)) & 0xFFu);
-    }
-  }
-};
-
-// The same E4M3 decode through gfx950's packed conversion instruction (two
-// codes per instruction instead of a dozen integer operations per code).
-struct FP8HwT {
-  static constexpr int kEpc = 16;
-  static constexpr bool kScaled = true;
-  __device__ static __forceinline__ void decode(uint4 c, float* x) {
-    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
-      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
-      x[4 * i] = lo[0];
-      x[4 * i + 1] = lo[1];
-      x[4 * i + 2] = hi[0];
-      x[4 * i + 3] = hi[1];
-    }
-  }
-};
-
-struct Args {
-  const unsigned char* base;  // n x (DC * 16) bytes
-  int64_t n;
-  int32_t d;
-  int32_t dc;                 // 16-byte chunks per vector
-  const float* dim_scale;     // fp8 only
-  const uint32_t* graph;
-  int32_t R;
-  const uint32_t* entry;
-  int32_t s;
-  const float* queries;
-  int64_t nq;
-  int32_t K, L, metric;
-  uint32_t* out_ids;
-  float* out_d;
-  int32_t* out_ndc;
-  int32_t* out_hops;
-  int32_t vmode;       // visited form: 0 exact bitset, 1 hash, 2 tag cache
-  int32_t hash_log2;   // hash / cache: log2 of the number of entries
-  int32_t id_bits;     // cache: k, with every id < 2^k (k - (hash_log2 - 2) <= 15)
-  int32_t lds_per_wave;
-  const float* base_f32;  // FP32 vectors for the final rerank, or null
-  int32_t rerank;         // pool entries to rerank (<= 64 * PREG); -1: K of each query
-  // batched / persistent mode
-  const int32_t* qlist;   // query indices processed by this launch, or null (0..nlist)
-  int64_t nlist;          // number of entries of qlist (or queries)
-  const int32_t* L_arr;   // per-query pool size, or null (L)
-  const int32_t* K_arr;   // per-query result count, or null (K)
-  int32_t kstride;        // output row stride (>= every K)
-  uint32_t* counter;      // persistent work queue head, or null (one query per wave)
-  int64_t entry_group;    // > 0: query i uses entry[(i / entry_group) * s ...]; 0: all share
-  uint32_t* out_trace;    // nq x trace_cap expanded ids in expansion order, or null
-  int32_t trace_cap;
-};
 
 // ------------------------------------------------------------------ kernel
 // T: stored element type; DC: chunks per vector (0 = runtime, query in LDS);
@@ -878,8 +681,6 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-using KernelFn = void (*)(Args);
-
 struct Launch {
   KernelFn fn = nullptr;
   int preg = 0;
@@ -1074,6 +875,55 @@ int lds_layout(int preg, int R, int d, bool query_in_regs, int dtype, int kind, 
   return SSG_OK;
 }
 
+// Launch with two queries per wavefront (32 lanes each, ssg_groups.hip).
+// want: the caller's queries_per_wave (0 = the library's choice, 1, 2).
+// On success gp->fn is the kernel, or null when the one-query form runs
+// (want 1, or want 0 and the default or the shape says so); a shape that
+// cannot run grouped is an error only when the caller asked for 2.
+// vp->per_wave is the bytes of ONE query's LDS region.
+struct GroupPlan {
+  KernelFn fn = nullptr;
+  int preg = 0;
+  VisitedPlan vp;
+};
+int group_preg_for(int L) { return L <= 64 ? 2 : L <= 96 ? 3 : L <= 128 ? 4 : L <= 256 ? 8 : 0; }
+int default_queries_per_wave(int dtype) {
+  (void)dtype;
+  return 1;
+}
+int plan_groups(int want, int dtype, int dc, int L, int kind, int64_t n, bool rerank, int hl_req,
+                bool batched, GroupPlan* gp) {
+  gp->fn = nullptr;
+  if (want < 0 || want > 2) return fail(SSG_EINVAL, "queries_per_wave must be 0, 1 or 2");
+  if (want == 1 || (want == 0 && default_queries_per_wave(dtype) == 1)) return SSG_OK;
+  auto no = [&](const char* why) {
+    return want == 2 ? fail(SSG_EUNSUPPORTED, "two queries per wavefront: %s", why) : SSG_OK;
+  };
+  if (kind == 1 || kind == 3) return no("needs the tag-cache visited set");
+  const int preg = group_preg_for(L);
+  if (preg == 0) return no("needs L <= 256");
+  KernelFn fn = ssg_internal_group_kernel(dtype, dc, preg, 32, batched);
+  if (!fn) return no("no compiled shape for this dtype and dimension");
+  // default 2048 entries (4 KB): with two queries per wavefront LDS, not
+  // registers, bounds how many searches a compute unit holds
+  const int hl = hl_req > 0 ? hl_req : 11;
+  if (hl < 4 || hl > 15) return fail(SSG_EINVAL, "hash_log2 must be in [4, 15]");
+  int k = 0;
+  while (k < 32 && ((uint64_t)1 << k) < (uint64_t)n) ++k;
+  k = std::max(k, hl - 2);
+  if (k - (hl - 2) > 15) return no("the ids need visited-cache tags over 16 bits");
+  const int lcap = 32 * preg;
+  size_t table = (size_t)2 << hl;
+  if (rerank) table = std::max(table, (size_t)lcap * 8);
+  gp->fn = fn;
+  gp->preg = preg;
+  gp->vp.vmode = 2;
+  gp->vp.hash_log2 = hl;
+  gp->vp.id_bits = k;
+  gp->vp.per_wave = ((size_t)lcap * 8 + 64 * 8 + 64 * 4 + table + 15) & ~(size_t)15;
+  return SSG_OK;
+}
+
 
 }  // namespace
 
@@ -1181,22 +1031,35 @@ int ssg_search_ex(const void* base, int64_t n, int32_t d, int32_t dtype, const f
     if (o.rerank_k < 0) return fail(SSG_EINVAL, "rerank_k must be >= 0");
     a.rerank = std::min(std::max(o.rerank_k, K), L);
   }
-  VisitedPlan vp;
-  rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, o.exact_visited ? 3 : o.visited_kind, n,
-                  o.base_f32 != nullptr, o.hash_log2, &vp);
+  const int kind = o.exact_visited ? 3 : o.visited_kind;
+  if (kind < 0 || kind > 3) return fail(SSG_EINVAL, "visited_kind must be in [0, 3]");
+  GroupPlan gp;
+  rc = plan_groups(o.queries_per_wave, dtype, dc, L, kind, n, o.base_f32 != nullptr, o.hash_log2,
+                   false, &gp);
   if (rc) return rc;
+  VisitedPlan vp = gp.vp;
+  int qpw = 1;
+  if (gp.fn) {
+    lc.fn = gp.fn;
+    qpw = 2;
+  } else {
+    rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, kind, n, o.base_f32 != nullptr, o.hash_log2,
+                    &vp);
+    if (rc) return rc;
+  }
   a.vmode = vp.vmode;
   a.hash_log2 = vp.hash_log2;
   a.id_bits = vp.id_bits;
-  size_t per_wave = vp.per_wave;
+  const size_t per_wave = vp.per_wave * qpw;  // a grouped launch: one region per query
   if (per_wave * wpb > 64 * 1024) {
     wpb = (int)((64 * 1024) / per_wave);
     if (wpb < 1) return fail(SSG_EUNSUPPORTED, "per-query LDS need %zu exceeds the CU", per_wave);
   }
-  a.lds_per_wave = (int)per_wave;
+  a.lds_per_wave = (int)vp.per_wave;
   const size_t lds = per_wave * wpb;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t blocks = (nq + wpb - 1) / wpb;
+  const int64_t per_block = (int64_t)wpb * qpw;
+  const int64_t blocks = (nq + per_block - 1) / per_block;
   if (blocks > 0x7FFFFFFF) return fail(SSG_EINVAL, "too many queries");
   hipLaunchKernelGGL(lc.fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
   hipError_t e = hipGetLastError();
@@ -1305,16 +1168,26 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     Launch lc = pick_launch(D->dtype, dc, preg, b.gather_variant, true);
     BucketLaunch bl{};
     Args& a = bl.a;
-    VisitedPlan vp;
     if (b.visited_kind < 0 || b.visited_kind > 2)
       return fail(SSG_EINVAL, "bucket %d: visited_kind must be 0, 1 or 2", i);
-    rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, b.visited_kind, D->n,
-                    D->base_f32 != nullptr, b.hash_log2, &vp);
+    GroupPlan gp;
+    rc = plan_groups(b.queries_per_wave, D->dtype, dc, b.max_L, b.visited_kind, D->n,
+                     D->base_f32 != nullptr, b.hash_log2, true, &gp);
     if (rc) return rc;
+    VisitedPlan vp = gp.vp;
+    int qpw = 1;
+    if (gp.fn) {
+      lc.fn = gp.fn;
+      qpw = 2;
+    } else {
+      rc = lds_layout(preg, D->R, D->d, lc.query_in_regs, D->dtype, b.visited_kind, D->n,
+                      D->base_f32 != nullptr, b.hash_log2, &vp);
+      if (rc) return rc;
+    }
     a.vmode = vp.vmode;
     a.hash_log2 = vp.hash_log2;
     a.id_bits = vp.id_bits;
-    const size_t per_wave = vp.per_wave;
+    const size_t per_wave = vp.per_wave * qpw;
     int wpb = b.waves_per_block > 0 ? b.waves_per_block : 1;
     while (wpb > 1 && per_wave * wpb > 64 * 1024) --wpb;
     if (per_wave > 64 * 1024) return fail(SSG_EUNSUPPORTED, "bucket %d: LDS need too large", i);
@@ -1336,7 +1209,7 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     a.out_d = D->out_dists;
     a.out_ndc = D->out_ndc;
     a.out_hops = D->out_hops;
-    a.lds_per_wave = (int)per_wave;
+    a.lds_per_wave = (int)vp.per_wave;
     a.base_f32 = D->rerank != 0 ? D->base_f32 : nullptr;
     a.rerank = D->rerank;
     a.qlist = b.qlist;
@@ -1357,7 +1230,7 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
         per_cu < 1)
       per_cu = 1;
     int64_t want = b.blocks > 0 ? b.blocks : (int64_t)per_cu * cus;
-    const int64_t need = (b.count + wpb - 1) / wpb;
+    const int64_t need = (b.count + (int64_t)wpb * qpw - 1) / ((int64_t)wpb * qpw);
     bl.blocks = (unsigned)std::max<int64_t>(1, std::min(want, std::max<int64_t>(need, 1)));
     out.push_back(bl);
   }

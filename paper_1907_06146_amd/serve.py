@@ -477,7 +477,8 @@ class GpuBatchDevice:
                 arr[i] = _lib.Bucket(dLK[2].data_ptr() + 4 * off, len(qi), mL,
                                      sh.get("gather_variant", 0), sh.get("hash_log2", 0),
                                      sh.get("waves_per_block", 0), sh.get("blocks", 0),
-                                     self.visited_map[sh.get("visited", "auto")])
+                                     self.visited_map[sh.get("visited", "auto")],
+                                     sh.get("queries_per_wave", 0))
             _lib.check(_lib.lib().ssg_search_batched(ctypes.byref(desc), arr, len(plan),
                                                      ctypes.c_void_p(s["wsp"]), s["wsb"],
                                                      ctypes.c_void_p(s["stream"].cuda_stream)))

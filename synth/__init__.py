@@ -13,4 +13,5 @@ from .gen import (  # noqa: F401
     indexed_query_ids,
     checksum,
     query_params,
+    steady_queries,
 )

@@ -41,7 +41,7 @@ CONFIGS: dict[str, dict] = {
     "c2": dict(kind="gmm_int", n=1_000_000, d=128, comps=1000, rank=16,
                nq_unindexed=10_000, nq_indexed=0, knn_k=100, l=100, R=50,
                alpha=60.0, s=10, L=100, K=100, L_sweep=_C2_SWEEP,
-               metric="l2", seed=2000),
+               metric="l2", seed=2000, nq_steady=100_000),
     "c2s": dict(kind="gmm_int", n=20_000, d=128, comps=40, rank=16,
                 nq_unindexed=500, nq_indexed=12, knn_k=100, l=100, R=50,
                 alpha=60.0, s=10, L=64, K=100, metric="l2", seed=2100),
@@ -205,6 +205,16 @@ def queries(cfg, base: np.ndarray | None = None) -> np.ndarray:
             base = base_vectors(cfg)
         q = np.concatenate([q, base[ids]], axis=0)
     return np.ascontiguousarray(q, dtype=np.float32)
+
+
+def steady_queries(cfg) -> np.ndarray:
+    """A second, larger set of unindexed queries from the same mixture (its
+    own stream, seed + 5), all distinct from each other and from the main
+    set, for throughput measured with the device full of searches."""
+    cfg = _cfg(cfg)
+    _, p = _params(cfg)
+    rng = np.random.default_rng(cfg["seed"] + 5)
+    return np.ascontiguousarray(_draw(cfg, p, rng, cfg["nq_steady"]), dtype=np.float32)
 
 
 def query_params(cfg) -> tuple[np.ndarray, np.ndarray]:
