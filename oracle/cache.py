@@ -14,6 +14,13 @@ A cache directory ``data/<workload>/`` holds plain ``.npy`` arrays and a
   oracle_L<L>_{ids,d,ndc,hops}.npy  Alg. 1 results of the oracle at pool L
   sweep.json     per-L recall / NDC / hops / CPU time of the oracle
 
+Compact copies for shipping (written by ``oracle/pack_cache.py``; the loader
+uses them when the plain files are absent):
+  graph_deg.npy   uint8 [n]        row lengths (replaces graph_off)
+  graph_bits.npy  uint64 [words]   graph_ids at meta["graph_bits"] bits per
+                                   id, 64 ids per block of graph_bits words
+  gt10_ids.npy    uint32 [nq, 10]  the first 10 columns of gt_ids
+
 The base vectors and queries are not stored: they are regenerated from the
 seed by ``synth`` and checked against the recorded checksums.
 """
@@ -83,16 +90,64 @@ def load_meta(name: str):
         return json.load(f)
 
 
+def pack_ids(ids: np.ndarray, bits: int) -> np.ndarray:
+    """Pack uint32 values below 2^bits into a uint64 stream, 64 values per
+    block of ``bits`` words (value j of a block at bit offset j * bits)."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    nb = -(-len(ids) // 64)
+    v = np.zeros((nb, 64), np.uint64)
+    v.reshape(-1)[:len(ids)] = ids
+    w = np.zeros((nb, bits + 1), np.uint64)
+    for j in range(64):
+        off = j * bits
+        k, sh = off // 64, off % 64
+        w[:, k] |= v[:, j] << np.uint64(sh)
+        if sh + bits > 64:
+            w[:, k + 1] |= v[:, j] >> np.uint64(64 - sh)
+    return np.ascontiguousarray(w[:, :bits]).reshape(-1)
+
+
+def unpack_ids(words: np.ndarray, bits: int, count: int) -> np.ndarray:
+    """Inverse of ``pack_ids``: the first ``count`` values as uint32."""
+    w = np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, bits)
+    w = np.concatenate([w, np.zeros((len(w), 1), np.uint64)], axis=1)
+    mask = np.uint64((1 << bits) - 1)
+    out = np.empty((len(w), 64), np.uint64)
+    for j in range(64):
+        off = j * bits
+        k, sh = off // 64, off % 64
+        x = w[:, k] >> np.uint64(sh)
+        if sh + bits > 64:
+            x |= w[:, k + 1] << np.uint64(64 - sh)
+        out[:, j] = x & mask
+    return out.reshape(-1)[:count].astype(np.uint32)
+
+
 def load(name: str, key: str, mmap: bool = False):
     if key == "graph":
-        off = np.load(os.path.join(path(name), "graph_off.npy"), allow_pickle=False)
-        ids = np.load(os.path.join(path(name), "graph_ids.npy"), allow_pickle=False)
-        return _from_csr(off, ids, load_meta(name)["R"])
+        d = path(name)
+        R = load_meta(name)["R"]
+        if os.path.exists(os.path.join(d, "graph_off.npy")):
+            off = np.load(os.path.join(d, "graph_off.npy"), allow_pickle=False)
+        else:
+            deg = np.load(os.path.join(d, "graph_deg.npy"), allow_pickle=False)
+            off = np.zeros(len(deg) + 1, np.int64)
+            np.cumsum(deg, out=off[1:])
+        if os.path.exists(os.path.join(d, "graph_ids.npy")):
+            ids = np.load(os.path.join(d, "graph_ids.npy"), allow_pickle=False)
+        else:
+            words = np.load(os.path.join(d, "graph_bits.npy"), allow_pickle=False)
+            ids = unpack_ids(words, load_meta(name)["graph_bits"], int(off[-1]))
+        return _from_csr(off, ids, R)
+    if key == "gt10_ids" and not os.path.exists(os.path.join(path(name), "gt10_ids.npy")):
+        return np.ascontiguousarray(load(name, "gt_ids")[:, :10])
     p = os.path.join(path(name), key + ".npy")
     return np.load(p, mmap_mode="r" if mmap else None, allow_pickle=False)
 
 
 def exists(name: str, key: str) -> bool:
     if key == "graph":
-        key = "graph_off"
+        return any(os.path.exists(os.path.join(path(name), k + ".npy")) for k in ("graph_off", "graph_deg"))
+    if key == "gt10_ids" and exists(name, "gt_ids"):
+        return True
     return os.path.exists(os.path.join(path(name), key + ".npy"))

@@ -172,19 +172,22 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       }
     }
   };
-  auto finish = [&](Pass& ps, int c0) {
-    float acc[NP];
+  // Keys of the pass set at c0 (m = the batch size, so that a batch that
+  // fits the first pass computes only that pass). The metric and the pass
+  // count are uniform, so both are chosen by one branch.
+  auto finish = [&](Pass& ps, int c0, int m) {
+    auto run = [&](auto ip_c, auto np_c) {
+      constexpr bool IP = decltype(ip_c)::value;
+      constexpr int NPL = decltype(np_c)::value;
+      float acc[NPL];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+      for (int p = 0; p < NPL; ++p) acc[p] = 0.f;
     if constexpr (kCompiled) {
       // with the query in LDS, re-read it per pass instead of letting the
       // compiler keep a register copy (the point is to free those registers)
       if constexpr (!kQueryInRegs) __asm__ volatile("" ::: "memory");
-      // the metric is uniform: branch once per pass, not per element
-      auto accumulate = [&](auto ip_c) {
-        constexpr bool IP = decltype(ip_c)::value;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
+        for (int p = 0; p < NPL; ++p) {
 #pragma unroll
           for (int t = 0; t < NCH; ++t) {
             const int ch = g + G * t;
@@ -212,12 +215,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
             }
           }
         }
-      };
-      if (ip) accumulate(std::true_type{});
-      else accumulate(std::false_type{});
     } else {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
+      for (int p = 0; p < NPL; ++p) {
         if (ps.vp[p]) {
           const uint4* vec = reinterpret_cast<const uint4*>(a.base + (size_t)ps.idp[p] * a.dc * 16);
 #pragma unroll 4
@@ -234,9 +234,20 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       }
     }
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      acc[p] = group_sum<G>(acc[p], lane);
-      if (ps.vp[p] && g == 0) bkeys[c0 + p * CPP + grp] = make_key(ip ? -acc[p] : acc[p], ps.idp[p]);
+      for (int p = 0; p < NPL; ++p) {
+        acc[p] = group_sum<G>(acc[p], lane);
+        if (ps.vp[p] && g == 0)
+          bkeys[c0 + p * CPP + grp] = IP ? make_key(-acc[p], ps.idp[p]) : make_key_nonneg(acc[p], ps.idp[p]);
+      }
+    };
+    using One = std::integral_constant<int, 1>;
+    using All = std::integral_constant<int, NP>;
+    if (NP == 1 || c0 + CPP >= m) {
+      if (ip) run(std::true_type{}, One{});
+      else run(std::false_type{}, One{});
+    } else {
+      if (ip) run(std::true_type{}, All{});
+      else run(std::false_type{}, All{});
     }
   };
   // keys of bids[first * CPP * NP .. m) (the passes before `first` are done)
@@ -244,7 +255,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     for (int c0 = first * CPP * NP; c0 < m; c0 += CPP * NP) {
       Pass ps;
       issue(ps, c0, m);
-      finish(ps, c0);
+      finish(ps, c0, m);
     }
     wave_sync();
   };
@@ -301,7 +312,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       if (lane < m) best = min(best, bkeys[lane]);
       wave_sync();
     }
-    best = wave_min64(best);
+    best = wave_min64_split(best);
     ndc = a.s;
     if (lane == 0) pool[0] = best | 1ull;
     size = 1;
@@ -363,7 +374,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     ndc += m;
     uint64_t b = kNoKey;
     if (m > 0) {
-      if constexpr (kPipe) finish(pend, 0);
+      if constexpr (kPipe) finish(pend, 0, m);
       batch_keys(m, kPipe ? 1 : 0);
       b = lane < m ? bkeys[lane] : kNoKey;
       if (size == L) {
@@ -401,7 +412,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     // u_spec, u_spec keeps its pool position (< L).
     bool more = u != kNoKey;
     if (__ballot(b < u)) {
-      u = wave_min64(b);  // below u_spec, so the smallest unchecked key
+      u = wave_min64_split(b);  // below u_spec, so the smallest unchecked key
       int rank_u = 0;     // (no new key is below u)
 #pragma unroll
       for (int k = 0; k < PREG; ++k) rank_u += __popcll(__ballot(pool[k] < u));
@@ -466,6 +477,21 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
     const int d4 = a.d >> 2;
     const float4* q4 = reinterpret_cast<const float4*>(q);
+    const int l16 = lane & 15;
+    // compiled dimension: the query's chunks stay in registers and each round
+    // issues every load of U candidate groups (4 candidates each, 16 lanes per
+    // candidate, NR float4 per lane) before the first is used
+    constexpr int D4 = kCompiled ? DC * EPC / 4 : 1;
+    constexpr int NR = (D4 + 15) / 16;
+    constexpr int U = NR >= 4 ? 1 : 4 / NR;
+    float4 qr[NR];
+    if constexpr (kCompiled) {
+#pragma unroll
+      for (int t = 0; t < NR; ++t) {
+        const int ch = l16 + 16 * t;
+        qr[t] = D4 % 16 == 0 || ch < D4 ? q4[ch] : make_float4(0, 0, 0, 0);
+      }
+    }
     for (int c0 = 0; c0 < rr; c0 += 64) {
       const int cm = min(64, rr - c0);
       // ids of pool entries c0 .. c0+cm-1 (entry i sits in lane i % 64, slot i / 64)
@@ -473,9 +499,43 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
       for (int k = 0; k < PREG; ++k)
         if (k == (c0 >> 6) && lane < cm) rids[lane] = key_id(pool[k]);
       wave_sync();
+      if constexpr (kCompiled) {
+        for (int j0 = 0; j0 < cm; j0 += 4 * U) {
+          uint32_t idr[U];
+          float4 xr[U][NR];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int c = j0 + 4 * u + (lane >> 4);
+            idr[u] = c < cm ? rids[c] : 0u;  // past the list: row 0, discarded
+            const float4* x4 = reinterpret_cast<const float4*>(a.base_f32 + (size_t)idr[u] * a.d);
+#pragma unroll
+            for (int t = 0; t < NR; ++t) {
+              const int ch = l16 + 16 * t;
+              xr[u][t] = D4 % 16 == 0 || ch < D4 ? x4[ch] : make_float4(0, 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int c = j0 + 4 * u + (lane >> 4);
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < NR; ++t) {
+              if (D4 % 16 == 0 || l16 + 16 * t < D4) {
+                acc = term(acc, qr[t].x, xr[u][t].x);
+                acc = term(acc, qr[t].y, xr[u][t].y);
+                acc = term(acc, qr[t].z, xr[u][t].z);
+                acc = term(acc, qr[t].w, xr[u][t].w);
+              }
+            }
+            acc = group_sum<16>(acc, lane);
+            if (c < cm && l16 == 0) rkeys[c0 + c] = make_key(ip ? -acc : acc, idr[u]);
+          }
+        }
+        wave_sync();
+        continue;
+      }
       for (int j0 = 0; j0 < cm; j0 += 4) {  // 16 lanes per candidate
         const int c = j0 + (lane >> 4);
-        const int l16 = lane & 15;
         float acc = 0.f;
         uint32_t id = 0;
         if (c < cm) {
@@ -754,6 +814,7 @@ struct Table<BF16T> {
         switch (variant) {
           case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg, batched); return l;
           case 4: l.query_in_regs = false; l.fn = pick_preg<BF16T, 16, 4, 1, true>(preg, batched); return l;
+          case 5: l.fn = pick_preg<BF16T, 16, 8, 2>(preg, batched); return l;  // 16 in flight
           default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;
         }
       case 120: l.fn = pick_preg<BF16T, 120, 32, 4>(preg, batched); return l;  // d = 960: 8
@@ -766,11 +827,16 @@ struct Table<BF16T> {
 };
 template <typename F>
 struct Fp8Table {
-  static Launch pick(int dc, int preg, bool batched) {
+  static Launch pick(int dc, int preg, bool batched, bool wide = false) {
     Launch l{nullptr, preg, true};
     switch (dc) {
       case 6: l.fn = pick_preg<F, 6, 4, 1>(preg, batched); return l;  // d = 96
-      case 8: l.fn = pick_preg<F, 8, 4, 1>(preg, batched); return l;  // d = 128
+      case 8:                                                          // d = 128
+        // 8 lanes per candidate in 2 passes (16 in flight): a lane holds 16
+        // query values and 16 scales instead of 32 each, so the kernel fits
+        // 4 waves per SIMD (measured 1.00 against 1.08 ms on 1M x 128)
+        if (wide) { l.fn = pick_preg<F, 8, 8, 2>(preg, batched); return l; }
+        l.fn = pick_preg<F, 8, 4, 1>(preg, batched); return l;
       case 60: l.fn = pick_preg<F, 60, 32, 4>(preg, batched); return l;  // d = 960: 8
       default: break;
     }
@@ -780,12 +846,13 @@ struct Fp8Table {
   }
 };
 // FP8: the conversion instruction by default (checked code by code against the
-// format definition); variant 1 keeps the bit-placement decode
+// format definition); variant 1 keeps the bit-placement decode, variant 2 the
+// 4-lane, one-pass gather shape
 template <>
 struct Table<FP8T> {
   static Launch pick(int dc, int preg, int variant, bool batched) {
     return variant == 1 ? Fp8Table<FP8T>::pick(dc, preg, batched)
-                        : Fp8Table<FP8HwT>::pick(dc, preg, batched);
+                        : Fp8Table<FP8HwT>::pick(dc, preg, batched, variant != 2);
   }
 };
 

@@ -72,7 +72,12 @@ __device__ __forceinline__ float unord_f32(uint32_t o) {
   return __uint_as_float(b);
 }
 __device__ __forceinline__ uint64_t make_key(float dist, uint32_t id) {
-  return ((uint64_t)ord_f32(dist) << 32) | ((uint64_t)id << 1);
+  return ((uint64_t)ord_f32(dist) << 32) | (uint32_t)(id << 1);
+}
+// The same key for a distance known to be >= +0 (a sum of squares that
+// starts at +0 is never -0): its order code is its bits with the sign set.
+__device__ __forceinline__ uint64_t make_key_nonneg(float dist, uint32_t id) {
+  return ((uint64_t)(__float_as_uint(dist) | 0x80000000u) << 32) | (uint32_t)(id << 1);
 }
 __device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)(k >> 1) & 0x7FFFFFFFu; }
 
@@ -129,6 +134,29 @@ __device__ __forceinline__ uint64_t dpp_min64(uint64_t v) {
   const uint32_t hi = __builtin_amdgcn_update_dpp(0xFFFFFFFFu, (uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
   const uint64_t o = ((uint64_t)hi << 32) | lo;
   return o < v ? o : v;
+}
+// Minimum of a 32-bit value over the wavefront: row shifts and row
+// broadcasts of the DPP unit, each folded into one v_min with its DPP
+// operand; a lane without a source lane keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min32(uint32_t v) {
+  return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
+  v = dpp_min32<0x111>(v);
+  v = dpp_min32<0x112>(v);
+  v = dpp_min32<0x114>(v);
+  v = dpp_min32<0x118>(v);
+  v = dpp_min32<0x142>(v);
+  v = dpp_min32<0x143>(v);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+// 64-bit minimum as two 32-bit ones: the high words, then the low words of
+// the lanes holding the smallest high word.
+__device__ __forceinline__ uint64_t wave_min64_split(uint64_t v) {
+  const uint32_t hi = wave_min32((uint32_t)(v >> 32));
+  const uint32_t lo = wave_min32((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0xFFFFFFFFu);
+  return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
   v = dpp_min64<0x111>(v);  // row_shr:1

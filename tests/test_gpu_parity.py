@@ -324,7 +324,7 @@ def test_c5_full_size_against_stored_oracle():
     rows = classify(base, q, gi, oi, "ip", 1e-5, gtr, o_trace)
     print(f"c5 L=96: {rows.summary()}", flush=True)
     assert_parity(rows, 0.999, "c5 L=96")
-    gt = cache.load("c5", "gt_ids")
+    gt = cache.load("c5", "gt10_ids")
     assert abs(core.recall_at(gi, gt, 10) - core.recall_at(oi, gt, 10)) <= 0.001
     # indexed queries (the last 5,000 rows) find themselves first
     ids = synth.indexed_query_ids(cfg)
