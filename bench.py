@@ -47,13 +47,43 @@ def recall_at(ids: np.ndarray, gt: np.ndarray, k: int) -> float:
     return hit / float(b.size)
 
 
-def algorithmic_bytes(ndc, hops, d, R, s, K, elem=4):
+def algorithmic_bytes(ndc, degsum, d, s, K, elem=4):
     """Bytes Alg. 1 itself must move per query: the query, the s entry
-    vectors, one fixed-width neighbour row (R ids) per expansion, one vector
-    per further distance computation, and the K (id, dist) outputs."""
+    vectors, the neighbour ids of every expanded node (4 bytes times the sum
+    of their out-degrees), one vector per further distance computation, and
+    the K (id, dist) outputs."""
+    ndc = np.asarray(ndc, np.float64)
+    degsum = np.asarray(degsum, np.float64)
+    return 4 * d + s * d * elem + 4 * degsum + (ndc - s) * d * elem + 8 * K
+
+
+def moved_bytes(ndc, hops, d, R, s, K, elem=4):
+    """The same with every expansion reading its whole fixed-width row (R
+    ids, what the n x R layout stores): the bytes the kernel moves."""
     ndc = np.asarray(ndc, np.float64)
     hops = np.asarray(hops, np.float64)
     return 4 * d + s * d * elem + hops * 4 * R + (ndc - s) * d * elem + 8 * K
+
+
+def dist_error(base, q, ids, dd):
+    """Relative error of returned distances against FP64 recomputation of
+    the same (query, id) pairs (padding skipped): (max, mean)."""
+    ids = np.asarray(ids)
+    ok = ids >= 0
+    x = base[np.where(ok, ids, 0).reshape(-1)].astype(np.float64).reshape(ids.shape + (base.shape[1],))
+    ref = ((q.astype(np.float64)[:, None, :] - x) ** 2).sum(-1)
+    rel = np.abs(np.asarray(dd, np.float64) - ref) / np.maximum(ref, 1e-30)
+    rel = rel[ok]
+    return (float(rel.max()), float(rel.mean())) if rel.size else (0.0, 0.0)
+
+
+def host_cores():
+    """Logical CPUs this process may run on, and the machine's count."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return avail, os.cpu_count() or avail
 
 
 def traffic_from_profile(kernel_tag: str):
@@ -150,6 +180,7 @@ def main():
     gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
     ondc = np.load(os.path.join(droot, f"oracle_L{L}_ndc.npy"), allow_pickle=False)
     ohops = np.load(os.path.join(droot, f"oracle_L{L}_hops.npy"), allow_pickle=False)
+    odeg = np.load(os.path.join(droot, f"oracle_L{L}_degsum.npy"), allow_pickle=False)
     log(f"data ready in {time.time() - t0:.1f}s: n={base.shape[0]} d={base.shape[1]} nq={len(q)} "
         f"R={gc['graph'].shape[1]} L={L} K={K}")
 
@@ -201,19 +232,17 @@ def main():
     qps = len(q) * a.steps / (gpu_ms / 1e3)
     log(f"{a.steps} steps: {gpu_ms:.3f} ms GPU ({launch_ms:.4f} ms/launch), wall {wall * 1e3:.1f} ms")
 
-    bq = algorithmic_bytes(ondc, ohops, base.shape[1], gc["graph"].shape[1], cfg["s"], K)
+    R = gc["graph"].shape[1]
+    bq = algorithmic_bytes(ondc, odeg, base.shape[1], cfg["s"], K)
     bytes_launch = float(bq.sum())
     achieved = bytes_launch / (launch_ms / 1e3) / 1e9
+    moved = float(moved_bytes(ondc, ohops, base.shape[1], R, cfg["s"], K).sum())
     traffic = traffic_from_profile("c2_search_f32")
-    # steady state: the same queries tiled x10 (100,000), so the launch is not
-    # dominated by the latency of its last-started queries
-    tq10 = tq.repeat(10, 1)
-    ids10 = torch.empty((len(tq10), K), dtype=torch.int32, device=dev)
-    dd10 = torch.empty((len(tq10), K), dtype=torch.float32, device=dev)
-    ms10 = _time(lambda: search(tb, tg, te, tq10, K, L, out=(ids10, dd10), waves_per_block=a.waves_per_block,
-                                hash_log2=a.hash_log2, gather_variant=a.variant), 3, 1, stream)
-    del ids10, dd10, tq10
-    log(f"steady state (100,000 queries): {ms10:.3f} ms, {1e6 / ms10 * 1e3:.0f} queries/s")
+    # steady state: 100,000 further distinct queries (their own oracle NDC and
+    # expanded-row bytes), so the launch is not dominated by the latency of
+    # its last-started queries
+    steady = steady_state(tb, tg, te, K, L, cfg, droot, a, stream)
+    log(f"steady state: {steady}")
     ceiling = gather_ceiling(tb, base.shape[1] * 4, int(np.sum(ondc)))
     log(f"random {base.shape[1] * 4}-byte row gather ceiling: {ceiling:.0f} GB/s")
     out = {
@@ -238,19 +267,49 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_query": float(bq.mean()),
+                     "moved_bytes_per_query": moved / len(q),
+                     "moved_GBps": moved / (launch_ms / 1e3) / 1e9,
+                     "oracle_expanded_degree_mean": float(np.sum(odeg) / np.sum(ohops)),
                      "oracle_ndc_mean": float(np.mean(ondc)), "oracle_hops_mean": float(np.mean(ohops)),
                      "gpu_ndc_mean": float(gndc.mean()),
                      "gather_ceiling_GBps": ceiling, "frac_of_gather_ceiling": achieved / ceiling},
-        "steady_state_100k_queries": {"ms_per_launch": ms10, "qps": 1e5 / ms10 * 1e3,
-                                      "achieved_GBps": bytes_launch * 10 / (ms10 / 1e3) / 1e9,
-                                      "frac": bytes_launch * 10 / (ms10 / 1e3) / 1e9 / PEAK_HBM_GBS},
+        "steady_state_100k_queries": steady,
         "kernel_source": source_digest(),
     }
     if not a.no_forms:
-        out["forms"] = precision_forms(tb, tg, te, tq, K, L, gt, sweep, cfg, a, launch_ms)
+        out["forms"] = precision_forms(tb, tg, te, tq, K, L, gt, sweep, cfg, a, launch_ms, base, q)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(base, gc, q, K, L, cfg, a.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def steady_state(tb, tg, te, K, L, cfg, droot, a, stream):
+    """The FP32 search over the 100,000 steady-state queries (distinct from
+    the headline set and from each other): time per launch, throughput,
+    algorithmic bytes from their own oracle counts, and agreement of the
+    first 10 ids with the oracle's."""
+    import torch
+
+    import synth
+    from paper_1907_06146_amd import search
+    qs = synth.steady_queries(cfg)
+    ondc = np.load(os.path.join(droot, f"steady_L{L}_ndc.npy"), allow_pickle=False)
+    odeg = np.load(os.path.join(droot, f"steady_L{L}_degsum.npy"), allow_pickle=False)
+    oids = np.load(os.path.join(droot, f"steady_L{L}_ids10.npy"), allow_pickle=False)
+    gt = np.load(os.path.join(droot, "steady_gt_ids.npy"), allow_pickle=False)
+    tq = torch.from_numpy(qs).to(tb.device)
+    ids = torch.empty((len(qs), K), dtype=torch.int32, device=tb.device)
+    dd = torch.empty((len(qs), K), dtype=torch.float32, device=tb.device)
+    kw = dict(out=(ids, dd), waves_per_block=a.waves_per_block, hash_log2=a.hash_log2,
+              gather_variant=a.variant)
+    ms = _time(lambda: search(tb, tg, te, tq, K, L, **kw), 5, 1, stream)
+    got = ids[:, :10].cpu().numpy().view(np.uint32)
+    bq = algorithmic_bytes(ondc, odeg, qs.shape[1], cfg["s"], K)
+    gbs = float(bq.sum()) / (ms / 1e3) / 1e9
+    return {"queries": int(len(qs)), "ms_per_launch": ms, "qps": len(qs) / ms * 1e3,
+            "achieved_GBps": gbs, "frac": gbs / PEAK_HBM_GBS,
+            "first10_equal_oracle": float((got == oids).all(1).mean()),
+            "recall10": recall_at(got, gt, 10), "distinct_queries": True}
 
 
 def _time(fn, steps, warmup, stream):
@@ -292,7 +351,7 @@ def gather_ceiling(base_t, row_bytes, m, seed=0, rows_per_wave=16):
     return m * row_bytes / (ms / 1e3) / 1e9
 
 
-def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
+def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms, base_np, q_np):
     """BF16 and FP8-E4M3 storage (FP32 accumulation, FP32 rerank of the whole
     pool) on the same workload: for each form the smallest swept L whose GPU
     recall@10 is >= 0.95, and its throughput, against the FP32 search."""
@@ -319,14 +378,23 @@ def precision_forms(tb, tg, te, tq, K, L_fp32, gt, sweep, cfg, a, fp32_ms):
                 _, _, ndc, hops = search(codes, tg, te, tq, K, L, stats=True, **kw)
                 ndc = ndc.double().mean().item()
                 hops = hops.double().mean().item()
+                ids_h, dd_h = search(codes, tg, te, tq, K, L, **kw)
+                torch.cuda.synchronize()
+                emax, emean = dist_error(base_np, q_np, ids_h.cpu().numpy(), dd_h.cpu().numpy())
+                # the search phase alone: its distances are those of the stored codes
+                si, sd = search(codes, tg, te, tq, K, L, dim_scale=scale)
+                torch.cuda.synchronize()
+                smax, smean = dist_error(base_np, q_np, si.cpu().numpy(), sd.cpu().numpy())
                 eb = 2 if fmt == "bf16" else 1
                 bq = 4 * d + cfg["s"] * d * eb + hops * 4 * tg.shape[1] + (ndc - cfg["s"]) * d * eb \
                     + min(L, K) * d * 4 + 8 * K
                 ceil = gather_ceiling(codes, d * eb, int(nq * ndc))
                 best = {"L": L, "recall10": r10, "ms_per_step": ms, "qps": nq / ms * 1e3,
                         "speedup_vs_fp32": fp32_ms / ms, "gpu_ndc_mean": ndc,
-                        "bytes_per_query": bq, "achieved_GBps": bq * nq / (ms / 1e3) / 1e9,
-                        "gather_ceiling_GBps": ceil, "rerank": "fp32, whole pool"}
+                        "moved_bytes_per_query": bq, "moved_GBps": bq * nq / (ms / 1e3) / 1e9,
+                        "gather_ceiling_GBps": ceil, "rerank": "fp32, whole pool",
+                        "dist_rel_err_vs_fp64": {"max": emax, "mean": emean},
+                        "search_phase_dist_rel_err_vs_fp64": {"max": smax, "mean": smean}}
                 break
         forms[fmt] = best
         log(f"form {fmt}: {best}")
@@ -786,18 +854,19 @@ def bench_precision_c3(a):
                 ms = _time(lambda: search(cb, tg, te, tq, K, L, **kw), a.steps, a.warmup, stream)
                 ndc_m = ndc.double().mean().item()
                 hops_m = hops.double().mean().item()
-                bq = algorithmic_bytes(ndc_m, hops_m, d, tg.shape[1], cfg["s"], K, elem[fmt]) \
+                bq = moved_bytes(ndc_m, hops_m, d, tg.shape[1], cfg["s"], K, elem[fmt]) \
                     + (L * d * 4 if rr else 0)
                 row = {"L": L, "form": fmt + ("+fp32 rerank" if rr else ""),
                        "recall10": recall_at(ids_h, gt, 10), "oracle_recall10": orc[L]["recall10"],
                        "ms": ms, "qps": nq / ms * 1e3, "ndc": ndc_m, "hops": hops_m,
-                       "bytes_per_query": bq, "GBps": bq * nq / (ms / 1e3) / 1e9,
+                       "moved_bytes_per_query": bq, "moved_GBps": bq * nq / (ms / 1e3) / 1e9,
                        "dist_rel_err_max": emax, "dist_rel_err_mean": emean}
                 rows.append(row)
                 log(row)
-    # steady state: the 1,000 queries tiled 16 times (one launch fills the device)
+    # steady state: 16,000 further distinct queries (one launch fills the device)
+    import synth
     steady = {}
-    tq16 = tq.repeat(16, 1).contiguous()
+    tq16 = torch.from_numpy(synth.steady_queries(cfg)).to(dev)
     Ls = 200
     for fmt in ("fp32", "bf16", "fp8"):
         cb, sc = codes[fmt]
@@ -809,7 +878,7 @@ def bench_precision_c3(a):
         log(f"steady {fmt}: {steady[fmt]}")
     return {"metric": "queries/s and recall@10 per storage precision (GIST-shaped 1M x 960, 1 GPU)",
             "unit": "queries/s", "n_gpus": 1, "workload": "gist-shaped synthetic 1,000,000 x 960 in "
-            "[0, 1], 1,000 queries, K = 10, squared L2", "rows": rows, "steady_state_16k": steady,
+            "[0, 1], 1,000 queries, K = 10, squared L2", "rows": rows, "steady_state_16k_distinct": steady,
             "data": "synthetic (seeded)"}
 
 
@@ -950,7 +1019,9 @@ def cpu_baseline(base, gc, q, K, L, cfg, sample):
     finally:
         core.threads(threads)
     log(f"cpu oracle: {m1} queries in {el1:.2f}s on 1 thread")
+    avail, total = host_cores()
     return {"value": reps * m / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "threads": threads, "host_cpus_available": avail, "host_cpus_total": total,
             "sample": f"{reps} passes over {m} of the {len(q)} queries, same graph, L={L}, "
                       f"K={K}, FP64, {el:.1f} s",
             "single_thread": {"value": m1 / el1, "unit": "queries/s",

@@ -12,7 +12,10 @@ Steps (all FP64 oracle code, no GPU):
      recording ids, keys, NDC and hops as the stored expected values;
   6. for workloads with a steady-state query set (``nq_steady``): its exact
      top 10 and Alg. 1's first 10 ids, NDC and hops at the operating pool
-     size.
+     size;
+  7. at the operating pool size, each query's sum of out-degrees over the
+     nodes Alg. 1 expanded (from its expansion record): the neighbour-row
+     bytes the search must read are 4 times that sum.
 The kNN graph is kept under data/_cpu/ (not needed by GPU runs).
 """
 
@@ -115,7 +118,34 @@ def build(name: str, sweep: bool, expand: str, sweep_only: bool = False):
             json.dump(dict(rows=rows, L_op=op[0] if op else None), f, indent=1)
     if cfg.get("nq_steady"):
         steady(name, cfg, base, g, entry, L_op)
+    degsums(name, cfg, base, g, entry, L_op)
     log(name, "done", f"{time.time() - t0:.1f}s", "L_op", L_op)
+
+
+def degsum_of(base, g, entry, q, K, L, metric):
+    """Per query: the sum of the out-degrees of the nodes Alg. 1 expanded."""
+    deg = (g != core.SENT).sum(1).astype(np.int64)
+    out = np.empty(len(q), np.int64)
+    for lo in range(0, len(q), 10_000):
+        qq = q[lo:lo + 10_000]
+        _, _, _, hops, tr = core.search(base, g, entry, qq, K, L, metric, trace=1)
+        cap = int(hops.max())
+        _, _, _, hops, tr = core.search(base, g, entry, qq, K, L, metric, trace=cap)
+        valid = tr != core.SENT
+        out[lo:lo + len(qq)] = np.where(valid, deg[np.where(valid, tr, 0).astype(np.int64)], 0).sum(1)
+    return out
+
+
+def degsums(name, cfg, base, g, entry, L):
+    t = time.time()
+    q = synth.queries(cfg, base)
+    arrays = {f"oracle_L{L}_degsum": degsum_of(base, g, entry, q, cfg["K"], L, cfg["metric"])}
+    if cfg.get("nq_steady"):
+        arrays[f"steady_L{L}_degsum"] = degsum_of(base, g, entry, synth.steady_queries(cfg), cfg["K"], L,
+                                                  cfg["metric"])
+    cache.save(name, arrays, {})
+    log("expanded-row degree sums", f"L={L}", f"{time.time() - t:.1f}s",
+        {k: float(v.mean()) for k, v in arrays.items()})
 
 
 def steady(name, cfg, base, g, entry, L):
@@ -140,8 +170,17 @@ def main():
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--sweep-only", action="store_true")
     ap.add_argument("--expand", default="literal", choices=["literal", "hop1first"])
+    ap.add_argument("--degsum-only", action="store_true",
+                    help="only step 7, at the stored operating pool size")
     a = ap.parse_args()
     for nm in a.names:
+        if a.degsum_only:
+            core.lib()
+            cfg = synth.CONFIGS[nm]
+            sw = os.path.join(cache.path(nm), "sweep.json")
+            L = (json.load(open(sw))["L_op"] if os.path.exists(sw) else None) or cfg["L"]
+            degsums(nm, cfg, synth.base_vectors(cfg), cache.load(nm, "graph"), cache.load(nm, "entry_ids"), L)
+            continue
         build(nm, a.sweep, a.expand, a.sweep_only)
 
 

@@ -45,10 +45,17 @@ CONFIGS: dict[str, dict] = {
     "c2s": dict(kind="gmm_int", n=20_000, d=128, comps=40, rank=16,
                 nq_unindexed=500, nq_indexed=12, knn_k=100, l=100, R=50,
                 alpha=60.0, s=10, L=64, K=100, metric="l2", seed=2100),
+    # the exact-SSG study (10,000 points, like the paper's SIFT10K experiment):
+    # a low-intrinsic-dimension set (rank-4 clusters), on which the 30-degree
+    # SSG keeps a few hundred edges per node, and the SIFT-shaped mixture
+    "ssg10k": dict(kind="gmm_int", n=10_000, d=128, comps=10, rank=4,
+                   nq_unindexed=1_000, nq_indexed=0, s=10, metric="l2", seed=2300),
+    "ssg10k_r16": dict(kind="gmm_int", n=10_000, d=128, comps=10, rank=16,
+                       nq_unindexed=1_000, nq_indexed=0, s=10, metric="l2", seed=2400),
     "c3": dict(kind="dirichlet", n=1_000_000, d=960, comps=500, rank=20, eps=0.003,
                nq_unindexed=1_000, nq_indexed=0, knn_k=100, l=500, R=50,
                alpha=60.0, s=10, L=200, K=10, L_sweep=list(range(100, 401, 50)),
-               metric="l2", seed=3000),
+               metric="l2", seed=3000, nq_steady=16_000),
     "c3s": dict(kind="dirichlet", n=8_000, d=960, comps=20, rank=20, eps=0.003,
                 nq_unindexed=100, nq_indexed=4, knn_k=60, l=120, R=50,
                 alpha=60.0, s=10, L=100, K=10, metric="l2", seed=3100),
