@@ -21,7 +21,9 @@
  *    work enqueued. A launch failure returns SSG_EDEVICE. The message of the
  *    last failing call on the calling thread is returned by ssg_last_error().
  *  - No C++ exception crosses the ABI. The library keeps no mutable global
- *    state except the thread-local error string; it is reentrant.
+ *    state except the thread-local error string and, for
+ *    ssg_search_batched_noalloc, one counter array per device (and its
+ *    looked-up address); every other entry point is reentrant.
  *  - Distances are returned as squared Euclidean distance (same order as the
  *    Euclidean distance of the paper's notation) or, for SSG_IP, as the
  *    negative inner product. Results are sorted ascending by (dist, id).
@@ -219,6 +221,25 @@ size_t ssg_batch_workspace_bytes(int32_t nb);
  * return. Returns SSG_OK or a negative status. */
 int ssg_search_batched(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
                        void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * ssg_search_batched_noalloc -- ssg_search_batched for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid allocation): the work-queue counters live in a fixed
+ * array inside the library (SSG_NOALLOC_SCRATCH_BYTES, one 256-byte slot per
+ * bucket), so no workspace is passed and nothing is allocated.
+ *   desc, buckets, nb, stream  as in ssg_search_batched; nb <= 64, else
+ *                              SSG_EINVAL
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (other streams, other threads) race and must be serialised
+ * by the caller. The counters are reset by a kernel at the start of each
+ * bucket, so nothing carries over from the previous call. The array's
+ * address is looked up on each device's first call (hipGetSymbolAddress);
+ * each device keeps its copy until the process ends.
+ */
+#define SSG_NOALLOC_SCRATCH_BYTES 16384
+int ssg_search_batched_noalloc(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
+                               void* stream);
 
 /* A captured HIP graph of the same work with the buckets on parallel graph
  * branches, replayed by ssg_batch_graph_launch as one launch. The device

@@ -28,7 +28,7 @@ EXPORTS = ("ssg_search", "ssg_search_ex", "ssg_quantize", "ssg_search_workspace_
            "ssg_batch_graph_destroy", "ssg_probe_gather", "ssg_knn_workspace_bytes",
            "ssg_knn_graph", "ssg_nssg_prune", "ssg_nssg_reverse_workspace_bytes", "ssg_nssg_reverse",
            "ssg_merge_shards", "ssg_exact_ssg_workspace_bytes", "ssg_exact_ssg",
-           "ssg_query_lds_bytes")
+           "ssg_query_lds_bytes", "ssg_search_batched_noalloc")
 
 
 class SSGError(RuntimeError):
@@ -125,6 +125,9 @@ def lib() -> ctypes.CDLL:
             L.ssg_exact_ssg.restype = ctypes.c_int
             L.ssg_query_lds_bytes.argtypes = [i32, i32, i32, i32, i64, i32, i32]
             L.ssg_query_lds_bytes.restype = sz
+            L.ssg_search_batched_noalloc.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(Bucket),
+                                                     i32, P]
+            L.ssg_search_batched_noalloc.restype = ctypes.c_int
             L.ssg_last_error.restype = ctypes.c_char_p
             L.ssg_version.restype = ctypes.c_char_p
             _lib = L

@@ -44,6 +44,8 @@ class BatchedSearch:
 
     base / base_f32 / dim_scale as in ``search``; L, K: int32 [nq] (host or
     device); rerank: 0 none, -1 the first K_i entries, > 0 a fixed count.
+    no_alloc: run through ssg_search_batched_noalloc (the work-queue counters
+    in the library's per-device array; calls on one device must not overlap).
     shapes: {max_L bucket capacity: dict(gather_variant, hash_log2,
     waves_per_block, blocks, visited, queries_per_wave)} from the autotuner
     (visited: "auto", "hash" or "cache", the form of the LDS visited set;
@@ -52,7 +54,7 @@ class BatchedSearch:
 
     def __init__(self, base, graph, entry_ids, queries, L, K, metric="l2", dim_scale=None,
                  base_f32=None, rerank=0, shapes=None, kstride=None, stats=False, use_graph=True,
-                 bounds=BUCKET_BOUNDS, trace=0):
+                 bounds=BUCKET_BOUNDS, trace=0, no_alloc=False):
         _need_cuda("base", base, tuple(_DTYPES))
         _need_cuda("graph", graph, (torch.int32, torch.uint32))
         _need_cuda("entry_ids", entry_ids, (torch.int32, torch.uint32))
@@ -72,10 +74,13 @@ class BatchedSearch:
         self.hops = torch.empty(self.nq, dtype=torch.int32, device=dev) if stats else None
         self.trace = torch.empty((self.nq, trace), dtype=torch.int32, device=dev) if trace > 0 else None
         nb = len(self.plan)
-        self.ws = torch.empty(_lib.lib().ssg_batch_workspace_bytes(nb) + 256, dtype=torch.uint8,
-                              device=dev)
-        wsp = (self.ws.data_ptr() + 255) & ~255
-        self._ws = (wsp, _lib.lib().ssg_batch_workspace_bytes(nb))
+        if no_alloc:  # the counters live in the library's own array
+            self.ws, wsp, self._ws = None, 0, (0, 0)
+        else:
+            self.ws = torch.empty(_lib.lib().ssg_batch_workspace_bytes(nb) + 256, dtype=torch.uint8,
+                                  device=dev)
+            wsp = (self.ws.data_ptr() + 255) & ~255
+            self._ws = (wsp, _lib.lib().ssg_batch_workspace_bytes(nb))
         self._keep = (base, graph, entry_ids, queries, dim_scale, base_f32)
         dtype = _DTYPES[base.dtype]
         self.desc = _lib.BatchDesc(
@@ -98,7 +103,8 @@ class BatchedSearch:
                                  sh.get("queries_per_wave", 0))
         self.buckets = arr
         self.graph = None
-        if use_graph:
+        self.no_alloc = no_alloc
+        if use_graph and not no_alloc:
             g = ctypes.c_void_p()
             _lib.check(_lib.lib().ssg_batch_graph_create(ctypes.byref(g), ctypes.byref(self.desc),
                                                          self.buckets, nb, ctypes.c_void_p(wsp),
@@ -107,7 +113,10 @@ class BatchedSearch:
 
     def run(self, stream=None):
         st = stream if stream is not None else torch.cuda.current_stream()
-        if self.graph is not None:
+        if self.no_alloc:  # counters in the library's own array: nothing allocated per call
+            rc = _lib.lib().ssg_search_batched_noalloc(ctypes.byref(self.desc), self.buckets,
+                                                       len(self.plan), ctypes.c_void_p(st.cuda_stream))
+        elif self.graph is not None:
             rc = _lib.lib().ssg_batch_graph_launch(self.graph, ctypes.c_void_p(st.cuda_stream))
         else:
             rc = _lib.lib().ssg_search_batched(ctypes.byref(self.desc), self.buckets,

@@ -49,6 +49,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -728,16 +729,21 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(const uint4* base, in
 }
 
 // ------------------------------------------------------------------ host side
-thread_local std::string g_err;
+// The calling thread's last error message: a fixed buffer, so that no call
+// (the error paths included) allocates host memory.
+struct ErrorText {
+  char text[512] = {0};
+  void clear() { text[0] = 0; }
+  const char* c_str() const { return text; }
+};
+thread_local ErrorText g_err;
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err.text, sizeof g_err.text, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -1014,7 +1020,7 @@ size_t ssg_query_lds_bytes(int32_t L, int32_t R, int32_t d, int32_t dtype, int64
   const int preg = preg_for(L);
   const Launch lc = pick_launch(dtype, d / epc, preg, 0, true);
   VisitedPlan vp;
-  const std::string keep = g_err;  // a size query leaves the error message alone
+  const ErrorText keep = g_err;  // a size query leaves the error message alone
   const int rc = lds_layout(preg, R, d, lc.query_in_regs, dtype, 0, n, rerank != 0, hash_log2, &vp);
   g_err = keep;
   return rc ? 0 : vp.per_wave;
@@ -1198,10 +1204,13 @@ struct BucketLaunch {
   uint32_t* counter;
 };
 
+constexpr int kMaxBuckets = 64;
+
+// Checks a batched call and fills out[0..nb) (capacity kMaxBuckets).
 int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* ws, size_t wsb,
-                    std::vector<BucketLaunch>& out) {
+                    BucketLaunch* out) {
   if (!D || !B) return fail(SSG_EINVAL, "descriptor or buckets is NULL");
-  if (nb < 1 || nb > 64) return fail(SSG_EINVAL, "nb must be in [1, 64] (got %d)", nb);
+  if (nb < 1 || nb > kMaxBuckets) return fail(SSG_EINVAL, "nb must be in [1, %d] (got %d)", kMaxBuckets, nb);
   if (!ws || wsb < ssg_batch_workspace_bytes(nb) || reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(SSG_ENOMEM, "workspace must be 256-byte aligned and hold %zu bytes",
                 ssg_batch_workspace_bytes(nb));
@@ -1224,7 +1233,6 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     return fail(SSG_EDEVICE, "cannot query the device");
   const int epc = D->dtype == SSG_F32 ? 4 : D->dtype == SSG_BF16 ? 8 : 16;
   const int dc = D->d / epc;
-  out.clear();
   for (int i = 0; i < nb; ++i) {
     const ssg_bucket& b = B[i];
     if (b.count < 0 || (b.count > 0 && !b.qlist)) return fail(SSG_EINVAL, "bucket %d: bad query list", i);
@@ -1299,7 +1307,7 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     int64_t want = b.blocks > 0 ? b.blocks : (int64_t)per_cu * cus;
     const int64_t need = (b.count + (int64_t)wpb * qpw - 1) / ((int64_t)wpb * qpw);
     bl.blocks = (unsigned)std::max<int64_t>(1, std::min(want, std::max<int64_t>(need, 1)));
-    out.push_back(bl);
+    out[i] = bl;
   }
   return SSG_OK;
 }
@@ -1307,6 +1315,40 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
 void enqueue_bucket(const BucketLaunch& bl, hipStream_t st) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, bl.counter, 0u, (int64_t)1);
   hipLaunchKernelGGL(bl.fn, dim3(bl.blocks), dim3(bl.threads), bl.lds, st, bl.a);
+}
+
+}  // namespace
+
+// Work-queue counters of ssg_search_batched_noalloc: one 256-byte slot per
+// bucket, at most kMaxBuckets buckets. Every device the library runs on holds
+// its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[SSG_NOALLOC_SCRATCH_BYTES];
+static_assert(SSG_NOALLOC_SCRATCH_BYTES == kMaxBuckets * 256, "one counter slot per bucket");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SSG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SSG_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SSG_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SSG_OK;
 }
 
 }  // namespace
@@ -1322,16 +1364,27 @@ size_t ssg_batch_workspace_bytes(int32_t nb) { return (size_t)std::max(nb, 0) * 
 
 int ssg_search_batched(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
                        void* workspace, size_t workspace_bytes, void* stream) {
-  std::vector<BucketLaunch> bl;
+  BucketLaunch bl[kMaxBuckets];
   int rc = prepare_batched(desc, buckets, nb, workspace, workspace_bytes, bl);
   if (rc) return rc;
   if (desc->nq == 0) { g_err.clear(); return SSG_OK; }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  for (const auto& b : bl) enqueue_bucket(b, st);
+  for (int i = 0; i < nb; ++i) enqueue_bucket(bl[i], st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SSG_EDEVICE, "launch: %s", hipGetErrorString(e));
   g_err.clear();
   return SSG_OK;
+}
+
+int ssg_search_batched_noalloc(const ssg_batch_desc* desc, const ssg_bucket* buckets, int32_t nb,
+                               void* stream) {
+  if (nb < 1 || nb > kMaxBuckets)
+    return fail(SSG_EINVAL, "nb must be in [1, %d] (got %d): the counters live in a %d-byte array",
+                kMaxBuckets, nb, SSG_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc) return rc;
+  return ssg_search_batched(desc, buckets, nb, ws, ssg_batch_workspace_bytes(nb), stream);
 }
 
 int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
@@ -1339,7 +1392,7 @@ int ssg_batch_graph_create(ssg_batch_graph** out, const ssg_batch_desc* desc,
                            size_t workspace_bytes) {
   if (!out) return fail(SSG_EINVAL, "out is NULL");
   *out = nullptr;
-  std::vector<BucketLaunch> bl;
+  BucketLaunch bl[kMaxBuckets];
   int rc = prepare_batched(desc, buckets, nb, workspace, workspace_bytes, bl);
   if (rc) return rc;
   hipStream_t cap = nullptr;
