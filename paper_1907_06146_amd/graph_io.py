@@ -1,9 +1,13 @@
 """Loader of NSSG graph caches into HBM.
 
-A cache directory holds the graph in compressed rows (``graph_off.npy``, int64
-[n+1], and ``graph_ids.npy``, uint32: row i is ids[off[i]:off[i+1]]), which the
-loader expands into the fixed-width n x R matrix the kernels read (ids, then
-0xFFFFFFFF padding: the n x m layout of Sec. 6.2),
+A cache directory holds the graph in compressed rows, which the loader
+expands into the fixed-width n x R matrix the kernels read (ids, then
+0xFFFFFFFF padding: the n x m layout of Sec. 6.2). Row lengths are
+``graph_off.npy`` (int64 [n+1], row i is ids[off[i]:off[i+1]]) or
+``graph_deg.npy`` (uint8 [n]); the ids are ``graph_ids.npy`` (uint32) or
+``graph_bits.npy``: each id in ``meta["graph_bits"]`` bits, 64 ids to a block
+of that many uint64 words, id j of a block at bit j * bits of the block read
+as one little-endian bit string.
 ``entry_ids.npy`` (uint32 [s], the navigating nodes) and ``meta.json`` (build
 parameters and checksums). Arrays are read with numpy's pickle-free loader.
 """
@@ -30,6 +34,30 @@ def _digest(a: np.ndarray) -> str:
     return h.hexdigest()[:16]
 
 
+def unpack_bits(words: np.ndarray, bits: int, count: int, chunk: int = 1 << 20) -> np.ndarray:
+    """The first ``count`` ids of a ``graph_bits`` stream, as uint32."""
+    if not 1 <= bits <= 25:
+        raise ValueError("ids must take 1..25 bits")
+    raw = np.ascontiguousarray(words, dtype="<u8").view(np.uint8)
+    blk = bits * 8  # bytes per block of 64 ids
+    if raw.size % blk or count > raw.size // blk * 64:
+        raise ValueError("graph_bits stream does not hold the ids")
+    raw = np.concatenate([raw, np.zeros(4, np.uint8)])  # a value may end in the last byte
+    bitpos = np.arange(64, dtype=np.int64) * bits
+    out = np.empty(count, np.uint32)
+    mask = np.uint32((1 << bits) - 1)
+    for v0 in range(0, count, chunk * 64):
+        v1 = min(count, v0 + chunk * 64)
+        v = np.arange(v0, v1, dtype=np.int64)
+        pos = (v >> 6) * blk * 8 + bitpos[v & 63]  # bit offset in the stream
+        at = pos >> 3
+        word = (raw[at].astype(np.uint32) | raw[at + 1].astype(np.uint32) << np.uint32(8)
+                | raw[at + 2].astype(np.uint32) << np.uint32(16)
+                | raw[at + 3].astype(np.uint32) << np.uint32(24))
+        out[v0:v1] = (word >> (pos & 7).astype(np.uint32)) & mask
+    return out
+
+
 def load(name: str, root: str | None = None, verify: bool = True) -> dict:
     """Read a cache: returns dict(graph, entry_ids, meta) as numpy arrays."""
     d = os.path.join(root or default_root(), name)
@@ -37,8 +65,16 @@ def load(name: str, root: str | None = None, verify: bool = True) -> dict:
         raise FileNotFoundError(f"graph cache {d} not found (built by the oracle's cache script)")
     with open(os.path.join(d, "meta.json")) as f:
         meta = json.load(f)
-    off = np.load(os.path.join(d, "graph_off.npy"), allow_pickle=False)
-    ids = np.load(os.path.join(d, "graph_ids.npy"), allow_pickle=False)
+    if os.path.exists(os.path.join(d, "graph_off.npy")):
+        off = np.load(os.path.join(d, "graph_off.npy"), allow_pickle=False)
+    else:
+        deg = np.load(os.path.join(d, "graph_deg.npy"), allow_pickle=False)
+        off = np.concatenate([[0], np.cumsum(deg, dtype=np.int64)])
+    if os.path.exists(os.path.join(d, "graph_ids.npy")):
+        ids = np.load(os.path.join(d, "graph_ids.npy"), allow_pickle=False)
+    else:
+        ids = unpack_bits(np.load(os.path.join(d, "graph_bits.npy"), allow_pickle=False),
+                          int(meta["graph_bits"]), int(off[-1]))
     R = int(meta["R"])
     n = len(off) - 1
     graph = np.full((n, R), 0xFFFFFFFF, np.uint32)
