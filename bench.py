@@ -424,7 +424,15 @@ def _load(name):
         raise SystemExit(f"regenerated {name} base vectors do not match the graph cache")
     q = synth.queries(cfg, base)
     droot = os.path.join(graph_io.default_root(), name)
-    gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
+    if os.path.exists(os.path.join(droot, "gt_ids.npy")):
+        gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
+    else:  # compact form: the first K_i ground-truth ids of each query, packed
+        rg = gc["meta"]["ragged"]["gt_ids"]
+        Kq = np.load(os.path.join(droot, "mixed_K.npy"), allow_pickle=False).astype(np.int64)
+        vals = graph_io.unpack_bits(np.load(os.path.join(droot, "gt_ids_bits.npy"), allow_pickle=False),
+                                    rg["bits"], int(Kq.sum()))
+        gt = np.full((len(Kq), rg["width"]), 0xFFFFFFFF, np.uint32)
+        gt[np.arange(rg["width"])[None, :] < Kq[:, None]] = vals
     return cfg, gc, base, q, gt
 
 

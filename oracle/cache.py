@@ -123,10 +123,41 @@ def unpack_ids(words: np.ndarray, bits: int, count: int) -> np.ndarray:
     return out.reshape(-1)[:count].astype(np.uint32)
 
 
+def ef_decode(low: np.ndarray, high: np.ndarray, l: int, H: int, deg: np.ndarray, n: int) -> np.ndarray:
+    """Ids of Elias-Fano coded rows (see oracle.pack_cache.ef_encode), in row
+    order, each row ascending."""
+    deg = np.asarray(deg, np.int64)
+    nnz = int(deg.sum())
+    field = np.zeros(len(deg) + 1, np.int64)
+    np.cumsum(deg + H, out=field[1:])
+    pos = np.flatnonzero(np.unpackbits(high, bitorder="little")[:field[-1]])
+    if len(pos) != nnz:
+        raise ValueError("Elias-Fano high bits do not match the row lengths")
+    row = np.repeat(np.arange(len(deg)), deg)
+    start = np.zeros(len(deg) + 1, np.int64)
+    np.cumsum(deg, out=start[1:])
+    hi = pos - field[row] - (np.arange(nnz) - start[row])
+    lo = unpack_ids(low, max(l, 1), nnz).astype(np.int64) if l else 0
+    out = (hi << l) | lo
+    if nnz and (out.max() >= n or hi.min() < 0):
+        raise ValueError("Elias-Fano rows out of range")
+    return out.astype(np.uint32)
+
+
 def load(name: str, key: str, mmap: bool = False):
     if key == "graph":
         d = path(name)
         R = load_meta(name)["R"]
+        ef = load_meta(name).get("graph_ef")
+        if ef and not os.path.exists(os.path.join(d, "graph_ids.npy")) and \
+                not os.path.exists(os.path.join(d, "graph_bits.npy")):
+            deg = np.load(os.path.join(d, "graph_deg.npy"), allow_pickle=False)
+            off = np.zeros(len(deg) + 1, np.int64)
+            np.cumsum(deg, out=off[1:])
+            ids = ef_decode(np.load(os.path.join(d, "graph_efl.npy"), allow_pickle=False),
+                            np.load(os.path.join(d, "graph_efh.npy"), allow_pickle=False),
+                            ef["l"], ef["H"], deg, load_meta(name)["n"])
+            return _from_csr(off, ids, R)
         if os.path.exists(os.path.join(d, "graph_off.npy")):
             off = np.load(os.path.join(d, "graph_off.npy"), allow_pickle=False)
         else:
@@ -139,6 +170,16 @@ def load(name: str, key: str, mmap: bool = False):
             words = np.load(os.path.join(d, "graph_bits.npy"), allow_pickle=False)
             ids = unpack_ids(words, load_meta(name)["graph_bits"], int(off[-1]))
         return _from_csr(off, ids, R)
+    rg = (load_meta(name) or {}).get("ragged", {}).get(key)
+    if rg and not os.path.exists(os.path.join(path(name), key + ".npy")):
+        # first K_i ids of each row, padded with SENT to the stored width
+        Kq = np.load(os.path.join(path(name), "mixed_K.npy"), allow_pickle=False).astype(np.int64)
+        vals = unpack_ids(np.load(os.path.join(path(name), key + "_bits.npy"), allow_pickle=False),
+                          rg["bits"], int(Kq.sum()))
+        vals[vals == load_meta(name)["n"]] = SENT  # an empty slot
+        out = np.full((len(Kq), rg["width"]), SENT, np.uint32)
+        out[np.arange(rg["width"])[None, :] < Kq[:, None]] = vals
+        return out
     if key == "gt10_ids" and not os.path.exists(os.path.join(path(name), "gt10_ids.npy")):
         return np.ascontiguousarray(load(name, "gt_ids")[:, :10])
     p = os.path.join(path(name), key + ".npy")
@@ -149,5 +190,7 @@ def exists(name: str, key: str) -> bool:
     if key == "graph":
         return any(os.path.exists(os.path.join(path(name), k + ".npy")) for k in ("graph_off", "graph_deg"))
     if key == "gt10_ids" and exists(name, "gt_ids"):
+        return True
+    if key in (load_meta(name) or {}).get("ragged", {}):
         return True
     return os.path.exists(os.path.join(path(name), key + ".npy"))

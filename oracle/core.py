@@ -268,11 +268,15 @@ def knn_graph_ivf(base, K: int, nlist: int, nprobe: int, seed: int, iters: int =
             continue
         cid = np.concatenate([order[starts[j]:starts[j + 1]] for j in probe[c]])
         ti = torch.from_numpy(cid)
-        s = torch.addmm(ny[ti].unsqueeze(0).expand(len(pts), -1), tb[torch.from_numpy(pts)],
-                        tb[ti].t(), beta=1.0, alpha=-2.0)
         k = min(C, len(cid))
-        idx = torch.topk(s, k, dim=1, largest=False).indices.numpy()
-        cand[pts, :k] = cid[idx]
+        cand_t = tb[ti].t().contiguous()
+        rows = max(256, (1 << 28) // max(1, len(cid)))  # bound the score block to ~1 GiB
+        for lo in range(0, len(pts), rows):
+            p = pts[lo:lo + rows]
+            s = torch.addmm(ny[ti].unsqueeze(0).expand(len(p), -1), tb[torch.from_numpy(p)],
+                            cand_t, beta=1.0, alpha=-2.0)
+            idx = torch.topk(s, k, dim=1, largest=False).indices.numpy()
+            cand[p, :k] = cid[idx]
         if verbose and c % 200 == 0:
             print(f"  ivf cell {c}/{nlist}", flush=True)
     skip = np.arange(n, dtype=np.int64)

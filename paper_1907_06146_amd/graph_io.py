@@ -7,7 +7,12 @@ expands into the fixed-width n x R matrix the kernels read (ids, then
 ``graph_deg.npy`` (uint8 [n]); the ids are ``graph_ids.npy`` (uint32) or
 ``graph_bits.npy``: each id in ``meta["graph_bits"]`` bits, 64 ids to a block
 of that many uint64 words, id j of a block at bit j * bits of the block read
-as one little-endian bit string.
+as one little-endian bit string. Search-only caches may instead hold rows
+sorted by id in Elias-Fano form (``graph_efl.npy``: low parts packed like
+graph_bits at l bits; ``graph_efh.npy``: bytes of one bit stream, least
+significant bit first, where row r owns deg_r + H bits and its i-th id sets
+bit (id >> l) + i of them; meta["graph_ef"] = dict(l, H, sorted_sha)): the
+search gives the same results for any order of a row.
 ``entry_ids.npy`` (uint32 [s], the navigating nodes) and ``meta.json`` (build
 parameters and checksums). Arrays are read with numpy's pickle-free loader.
 """
@@ -58,6 +63,24 @@ def unpack_bits(words: np.ndarray, bits: int, count: int, chunk: int = 1 << 20) 
     return out
 
 
+def decode_ef_rows(low: np.ndarray, high: np.ndarray, l: int, H: int, deg: np.ndarray) -> np.ndarray:
+    """Ids of Elias-Fano rows (row order, ascending within a row) as uint32."""
+    deg = np.asarray(deg, dtype=np.int64)
+    total = int(deg.sum())
+    width = deg + H
+    ends = np.cumsum(width)
+    ones = np.flatnonzero(np.unpackbits(np.asarray(high, np.uint8), bitorder="little"))
+    ones = ones[ones < (ends[-1] if len(ends) else 0)]
+    if len(ones) != total:
+        raise ValueError("Elias-Fano stream does not match the row lengths")
+    row = np.searchsorted(ends, ones, side="right")  # the field each set bit falls in
+    first = np.concatenate([[0], np.cumsum(deg)[:-1]])  # index of each row's first id
+    rank = np.arange(total, dtype=np.int64) - first[row]
+    hi = ones - (ends[row] - width[row]) - rank
+    lo = unpack_bits(low, l, total).astype(np.int64) if l > 0 else np.zeros(total, np.int64)
+    return ((hi << l) | lo).astype(np.uint32)
+
+
 def load(name: str, root: str | None = None, verify: bool = True) -> dict:
     """Read a cache: returns dict(graph, entry_ids, meta) as numpy arrays."""
     d = os.path.join(root or default_root(), name)
@@ -70,11 +93,18 @@ def load(name: str, root: str | None = None, verify: bool = True) -> dict:
     else:
         deg = np.load(os.path.join(d, "graph_deg.npy"), allow_pickle=False)
         off = np.concatenate([[0], np.cumsum(deg, dtype=np.int64)])
+    sha = meta.get("graph_sha")
     if os.path.exists(os.path.join(d, "graph_ids.npy")):
         ids = np.load(os.path.join(d, "graph_ids.npy"), allow_pickle=False)
-    else:
+    elif os.path.exists(os.path.join(d, "graph_bits.npy")):
         ids = unpack_bits(np.load(os.path.join(d, "graph_bits.npy"), allow_pickle=False),
                           int(meta["graph_bits"]), int(off[-1]))
+    else:
+        ef = meta["graph_ef"]
+        ids = decode_ef_rows(np.load(os.path.join(d, "graph_efl.npy"), allow_pickle=False),
+                             np.load(os.path.join(d, "graph_efh.npy"), allow_pickle=False),
+                             int(ef["l"]), int(ef["H"]), np.diff(off))
+        sha = ef["sorted_sha"]
     R = int(meta["R"])
     n = len(off) - 1
     graph = np.full((n, R), 0xFFFFFFFF, np.uint32)
@@ -86,7 +116,7 @@ def load(name: str, root: str | None = None, verify: bool = True) -> dict:
     entry = np.load(os.path.join(d, "entry_ids.npy"), allow_pickle=False)
     if graph.dtype != np.uint32 or graph.ndim != 2:
         raise ValueError("graph must be a 2-D uint32 array")
-    if verify and "graph_sha" in meta and _digest(graph) != meta["graph_sha"]:
+    if verify and sha is not None and _digest(graph) != sha:
         raise ValueError(f"graph checksum mismatch in {d}")
     return dict(graph=graph, entry_ids=entry.astype(np.uint32), meta=meta)
 

@@ -54,8 +54,9 @@ CONFIGS: dict[str, dict] = {
                        nq_unindexed=1_000, nq_indexed=0, s=10, metric="l2", seed=2400),
     "c3": dict(kind="dirichlet", n=1_000_000, d=960, comps=500, rank=20, eps=0.003,
                nq_unindexed=1_000, nq_indexed=0, knn_k=100, l=500, R=50,
-               alpha=60.0, s=10, L=200, K=10, L_sweep=list(range(100, 401, 50)),
-               metric="l2", seed=3000, nq_steady=16_000),
+               alpha=60.0, s=10, L=200, K=10, L_sweep=list(range(100, 501, 50)),
+               metric="l2", seed=3000, nq_steady=16_000,
+               knn="ivf", nlist=1000, nprobe=16, refine_J=32, refine_rounds=3),
     "c3s": dict(kind="dirichlet", n=8_000, d=960, comps=20, rank=20, eps=0.003,
                 nq_unindexed=100, nq_indexed=4, knn_k=60, l=120, R=50,
                 alpha=60.0, s=10, L=100, K=10, metric="l2", seed=3100),

@@ -74,3 +74,50 @@ def test_library_loader_loads_the_packed_graph(tmp_path, monkeypatch):
     with pytest.raises(ValueError):
         graph_io.unpack_bits(np.zeros(3, np.uint64), 20, 10)
     shutil.rmtree(d)
+
+
+def _random_csr(rng, n, R, empty_rows=True):
+    deg = rng.integers(0 if empty_rows else 1, R + 1, n)
+    off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    ids = np.concatenate([rng.choice(n, k, replace=False) for k in deg] or [np.zeros(0)]).astype(np.uint32)
+    return off, ids
+
+
+@pytest.mark.parametrize("n,R", [(2, 1), (50, 7), (3000, 40), (70_000, 20)])
+def test_elias_fano_rows_round_trip(n, R):
+    """Rows of a CSR graph, sorted and Elias-Fano coded: the oracle's decoder
+    and the package's own decoder both give the sorted rows back."""
+    from oracle import pack_cache
+    from paper_1907_06146_amd import graph_io
+    rng = np.random.default_rng(n)
+    off, ids = _random_csr(rng, n, R)
+    low, high, l, H, srt = pack_cache.ef_encode(off, ids, n)
+    deg = np.diff(off)
+    for r in range(min(n, 200)):  # each row sorted, same set of ids
+        a, b = off[r], off[r + 1]
+        assert np.array_equal(srt[a:b], np.sort(ids[a:b]))
+    assert np.array_equal(cache.ef_decode(low, high, l, H, deg, n), srt)
+    assert np.array_equal(graph_io.decode_ef_rows(low, high, l, H, deg), srt)
+    if len(ids) > 1000:  # close to log2(n / degree) + 2 bits per id
+        assert 8 * (low.nbytes + high.nbytes) / len(ids) < np.log2(n / deg.mean()) + 3
+
+
+def test_elias_fano_cache_loads_sorted_rows(tmp_path, monkeypatch):
+    from oracle import pack_cache
+    from paper_1907_06146_amd import graph_io
+    monkeypatch.setenv("SSG_DATA", str(tmp_path))
+    monkeypatch.setattr(pack_cache, "EF_WORKLOADS", ("v",))
+    rng = np.random.default_rng(2)
+    n, R = 1200, 13
+    off, ids = _random_csr(rng, n, R)
+    g = cache._from_csr(off, ids, R)
+    cache.save("v", dict(graph=g, entry_ids=np.arange(3, dtype=np.uint32)), dict(n=n, R=R))
+    pack_cache.pack("v")
+    d = cache.path("v")
+    for f in ("graph_off", "graph_ids", "graph_bits"):
+        os.remove(os.path.join(d, f + ".npy"))
+    want = np.sort(g, axis=1)  # SENT (the largest value) stays at the end of each row
+    assert np.array_equal(cache.load("v", "graph"), want)
+    out = graph_io.load("v", root=str(tmp_path))  # verifies the sorted-graph checksum
+    assert np.array_equal(out["graph"], want)
+    shutil.rmtree(d)

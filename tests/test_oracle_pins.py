@@ -181,3 +181,24 @@ def test_search_trace_matches_python_twin():
         # a shorter record is the prefix of the full one
         _, _, _, _, short = core.search(base, g, entry, q, K, L, trace=2)
         assert np.array_equal(short, ct[:, :2])
+
+
+def test_search_does_not_depend_on_the_order_of_a_row():
+    """Alg. 1 takes every neighbour of the expanded node and re-sorts the pool
+    by (distance, id): permuting the ids within each adjacency row changes no
+    result, no expansion count and no expansion record."""
+    rng = np.random.default_rng(8)
+    base = rng.integers(0, 40, (600, 16)).astype(np.float32)
+    knn, _ = core.knn_graph(base, 20)
+    entry = rng.choice(600, 5, replace=False).astype(np.uint32)
+    g = core.nssg_build(base, knn, 30, 12, 60.0, entry)["graph"]
+    perm = g.copy()
+    for r in range(len(perm)):
+        k = int((perm[r] != core.SENT).sum())
+        perm[r, :k] = rng.permutation(perm[r, :k])
+    assert not np.array_equal(perm, g)
+    q = rng.integers(0, 40, (50, 16)).astype(np.float32)
+    a = core.search(base, g, entry, q, 10, 40, trace=200)
+    b = core.search(base, perm, entry, q, 10, 40, trace=200)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
