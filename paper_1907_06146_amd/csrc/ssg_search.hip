@@ -818,10 +818,16 @@ struct Table<BF16T> {
         l.fn = pick_preg<BF16T, 12, 4, 1>(preg, batched); return l;
       case 16:                                                      // d = 128
         switch (variant) {
+          case 2: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;  // 16 in flight
           case 3: l.fn = pick_preg<BF16T, 16, 4, 2>(preg, batched); return l;
           case 4: l.query_in_regs = false; l.fn = pick_preg<BF16T, 16, 4, 1, true>(preg, batched); return l;
-          case 5: l.fn = pick_preg<BF16T, 16, 8, 2>(preg, batched); return l;  // 16 in flight
-          default: l.fn = pick_preg<BF16T, 16, 4, 1>(preg, batched); return l;
+          // 16 lanes per candidate, 2 passes (8 in flight): 80 VGPRs, so 6
+          // wavefronts per SIMD when the visited cache is 4 KB (hash_log2 11)
+          case 7: l.fn = pick_preg<BF16T, 16, 16, 2>(preg, batched); return l;
+          case 8: l.fn = pick_preg<BF16T, 16, 8, 1>(preg, batched); return l;  // 8 in flight, 82 VGPRs
+          // 8 lanes per candidate, 2 passes (16 in flight): measured 1.10 ms
+          // against 1.16 ms for the 4-lane shape on 10,000 queries of 1M x 128
+          default: l.fn = pick_preg<BF16T, 16, 8, 2>(preg, batched); return l;
         }
       case 120: l.fn = pick_preg<BF16T, 120, 32, 4>(preg, batched); return l;  // d = 960: 8
       default: break;
@@ -833,7 +839,7 @@ struct Table<BF16T> {
 };
 template <typename F>
 struct Fp8Table {
-  static Launch pick(int dc, int preg, bool batched, bool wide = false) {
+  static Launch pick(int dc, int preg, bool batched, int wide = 0) {
     Launch l{nullptr, preg, true};
     switch (dc) {
       case 6: l.fn = pick_preg<F, 6, 4, 1>(preg, batched); return l;  // d = 96
@@ -841,6 +847,7 @@ struct Fp8Table {
         // 8 lanes per candidate in 2 passes (16 in flight): a lane holds 16
         // query values and 16 scales instead of 32 each, so the kernel fits
         // 4 waves per SIMD (measured 1.00 against 1.08 ms on 1M x 128)
+        if (wide == 2) { l.fn = pick_preg<F, 8, 8, 1>(preg, batched); return l; }  // 8 in flight, 94 VGPRs
         if (wide) { l.fn = pick_preg<F, 8, 8, 2>(preg, batched); return l; }
         l.fn = pick_preg<F, 8, 4, 1>(preg, batched); return l;
       case 60: l.fn = pick_preg<F, 60, 32, 4>(preg, batched); return l;  // d = 960: 8
@@ -853,12 +860,12 @@ struct Fp8Table {
 };
 // FP8: the conversion instruction by default (checked code by code against the
 // format definition); variant 1 keeps the bit-placement decode, variant 2 the
-// 4-lane, one-pass gather shape
+// 4-lane, one-pass gather shape, variant 3 the 8-lane one-pass shape
 template <>
 struct Table<FP8T> {
   static Launch pick(int dc, int preg, int variant, bool batched) {
     return variant == 1 ? Fp8Table<FP8T>::pick(dc, preg, batched)
-                        : Fp8Table<FP8HwT>::pick(dc, preg, batched, variant != 2);
+                        : Fp8Table<FP8HwT>::pick(dc, preg, batched, variant == 3 ? 2 : variant == 2 ? 0 : 1);
   }
 };
 

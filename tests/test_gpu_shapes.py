@@ -79,9 +79,9 @@ def _check(fmt, base, deq, q, gi, gd, ghops, gtr, oi, od, ohops, otr, what):
 SHAPES = ([("f32", d, 0) for d in (32, 64, 96, 100, 200, 300, 960)]
           + [("f32", 128, v) for v in range(7)]
           + [("bf16", d, 0) for d in (64, 96, 200, 960)]
-          + [("bf16", 96, 4)] + [("bf16", 128, v) for v in (0, 3, 4, 5)]
+          + [("bf16", 96, 4)] + [("bf16", 128, v) for v in (0, 2, 3, 4, 7, 8)]
           + [("fp8", d, 0) for d in (64, 96, 960)]
-          + [("fp8", 128, v) for v in (0, 1, 2)])
+          + [("fp8", 128, v) for v in (0, 1, 2, 3)])
 
 
 @pytest.mark.parametrize("fmt,d,variant", SHAPES)
