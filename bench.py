@@ -33,9 +33,12 @@ def log(*a):
 
 
 def source_digest() -> str:
+    """sha1 prefix of the search kernels' sources (the kernel file and its
+    shared header)."""
     h = hashlib.sha1()
-    with open(os.path.join(ROOT, "paper_1907_06146_amd", "csrc", "ssg_search.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("ssg_search.hip", "ssg_search_common.h"):
+        with open(os.path.join(ROOT, "paper_1907_06146_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:12]
 
 
@@ -131,6 +134,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: 3 launches of the timed configuration, then a 1 GiB "
                          "element-wise copy whose bytes calibrate the counters; no output")
+    ap.add_argument("--pmc-form", default="f32", choices=["f32", "bf16", "fp8"],
+                    help="with --pmc-probe: the storage form searched (BF16 / FP8 with the FP32 "
+                         "rerank of every returned entry)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the index and every query "
@@ -140,7 +146,7 @@ def main():
     import torch
 
     import synth
-    from paper_1907_06146_amd import graph_io, search
+    from paper_1907_06146_amd import graph_io, quantize, search
 
     if a.workload == "exact":
         print(json.dumps(bench_exact(a)), flush=True)
@@ -198,8 +204,13 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     if a.pmc_probe:
+        if a.pmc_form == "f32":
+            codes, pkw = tb, kw
+        else:
+            codes, scale = quantize(tb, a.pmc_form)
+            pkw = dict(kw, dim_scale=scale, base_f32=tb, rerank_k=K)
         for _ in range(3):
-            search(tb, tg, te, tq, K, L, **kw)
+            search(codes, tg, te, tq, K, L, **pkw)
         torch.cuda.synchronize()
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)

@@ -481,10 +481,12 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
     const int l16 = lane & 15;
     // compiled dimension: the query's chunks stay in registers and each round
     // issues every load of U candidate groups (4 candidates each, 16 lanes per
-    // candidate, NR float4 per lane) before the first is used
+    // candidate, NR float4 per lane) before the first is used: up to 8 float4
+    // per lane in flight (16 candidates of 128 floats), so a pool of 80 takes
+    // 5 rounds of load latency
     constexpr int D4 = kCompiled ? DC * EPC / 4 : 1;
     constexpr int NR = (D4 + 15) / 16;
-    constexpr int U = NR >= 4 ? 1 : 4 / NR;
+    constexpr int U = NR >= 8 ? 1 : 8 / NR;
     float4 qr[NR];
     if constexpr (kCompiled) {
 #pragma unroll
