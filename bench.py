@@ -126,8 +126,12 @@ def main():
     ap.add_argument("--shards", type=int, default=4, help="sharded: number of shards")
     ap.add_argument("--offered-rps", type=float, default=4000.0, help="c5: request arrival rate")
     ap.add_argument("--requests", type=int, default=8000, help="c5: number of requests")
-    ap.add_argument("--oversubscribe", type=float, default=2.0,
-                    help="serving admission: LDS budget = this x the chip's LDS")
+    ap.add_argument("--scaling-mode", default="prefix", choices=["prefix", "density"],
+                    help="scaling: prefixes of the 1M set, or a fresh draw per n with n / 1,000 "
+                         "components (the same points per component at every n)")
+    ap.add_argument("--oversubscribe", type=float, default=6.0,
+                    help="serving admission: LDS budget = this x the chip's LDS (6: about the "
+                         "3 batch slots of 8,192 queries the count-based admission held)")
     ap.add_argument("--serve-data", default="c5", help="c5: index to serve (c5, or c4 for a smaller run)")
     ap.add_argument("--serve-mode", default="batch", choices=["batch", "request"],
                     help="c5: continuous batching of waiting requests, or one launch per request")
@@ -531,7 +535,9 @@ def bench_batched(a):
     qb, _ = quantize(tb, "bf16")
     tune_path = os.path.join(graph_io.default_root(), "autotune.json")
     for name, bse, kw in (("batched_fp32", tb, {}),
-                          ("batched_bf16_rerank", qb, dict(base_f32=tb, rerank=-1))):
+                          ("batched_bf16_rerank", qb, dict(base_f32=tb, rerank=-1)),
+                          ("batched_bf16_rerank_2k", qb, dict(base_f32=tb, rerank=-2)),
+                          ("batched_bf16_rerank_4k", qb, dict(base_f32=tb, rerank=-4))):
         t = time.time()
         shapes = tune(bse, tg, te, tq, Lq, Kq, "ip", sample=2048, reps=2, cache_path=tune_path, **kw)
         log(f"{name}: tuned in {time.time() - t:.1f}s: {shapes}")
@@ -541,7 +547,11 @@ def bench_batched(a):
         r = recall_mixed(ids, gt, Kq)
         same = float(np.mean((ids == ids_plain).all(1)))
         out[name] = {"ms": ms, "qps": nq / ms * 1e3, "recall_at_Ki": r, "speedup_vs_plain": ms_plain / ms,
-                     "rows_equal_to_plain": same, "shapes": {str(k): v for k, v in shapes.items()}}
+                     "rows_equal_to_plain": same, "shapes": {str(k): v for k, v in shapes.items()},
+                     "rerank": {0: "none", -1: "first K_i", -2: "first 2 K_i", -4: "first 4 K_i"}[
+                         kw.get("rerank", 0)]}
+        if name != "batched_fp32":
+            out[name]["speedup_vs_batched_fp32"] = out["batched_fp32"]["ms"] / ms
         log(f"{name}: {ms:.3f} ms, recall {r:.4f}, x{ms_plain / ms:.2f}")
         bs.close()
     out["value"] = out["batched_bf16_rerank"]["qps"]
@@ -686,17 +696,30 @@ def bench_scaling(a):
     from paper_1907_06146_amd import search
     from paper_1907_06146_amd.binding import knn_graph
 
+    import synth
     cfg, gc, base, q, gt_full = _load("c2")
     dev = torch.device("cuda:0")
-    tq = torch.from_numpy(q).to(dev)
-    qn = (tq.double() ** 2).sum(1, keepdim=True)
     stream = torch.cuda.current_stream()
     Ls = list(range(20, 101, 10)) + list(range(120, 301, 20))
+    if a.scaling_mode == "density":
+        # a fresh draw per n with n / 1,000 components: every size has the same
+        # points per component (1,000) and the same local structure
+        def data(n):
+            c = dict(synth.CONFIGS["c2"], n=n, comps=n // 1000, nq_unindexed=10_000, nq_indexed=0,
+                     seed=synth.CONFIGS["c2"]["seed"] + 97 + n // 62_500)
+            b = synth.base_vectors(c)
+            return b, synth.queries(c, b)
+    else:
+        def data(n):
+            return base[:n], q
     targets = (0.95, 0.99)
     lid = 13.0
     rows = []
     for n in (62_500, 125_000, 250_000, 500_000, 1_000_000):
-        tb = torch.from_numpy(base[:n]).to(dev)
+        bn, qq = data(n)
+        tb = torch.from_numpy(np.ascontiguousarray(bn)).to(dev)
+        tq = torch.from_numpy(qq).to(dev)
+        qn = (tq.double() ** 2).sum(1, keepdim=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         knn, _, _ = knn_graph(tb, cfg["knn_k"])
@@ -705,10 +728,10 @@ def bench_scaling(a):
         g, e, t_edge = _gpu_nssg(tb, knn, cfg, cfg["alpha"])
         # exact top 10 of each query over the prefix (integer data: every FP64
         # sum is exact), ties by id
-        gt = np.empty((len(q), 10), np.int64)
+        gt = np.empty((len(qq), 10), np.int64)
         tb64 = tb.double()
         xn = (tb64 ** 2).sum(1)
-        for lo in range(0, len(q), 1000):
+        for lo in range(0, len(qq), 1000):
             dd = qn[lo:lo + 1000] + xn[None, :] - 2.0 * (tq[lo:lo + 1000].double() @ tb64.t())
             key = dd * (n + 1) + torch.arange(n, device=dev, dtype=torch.float64)[None, :]
             gt[lo:lo + 1000] = torch.topk(key, 10, dim=1, largest=False).indices.cpu().numpy()
@@ -739,7 +762,7 @@ def bench_scaling(a):
                 L_t, ndc_t, hops_t = L0 + w * (L1 - L0), n0 + w * (n1 - n0), h0 + w * (h1 - h0)
             ms = _time(lambda: search(tb, g, e, tq, cfg["K"], curve[hit][0]), a.steps, a.warmup, stream)
             at[str(t)] = {"L_interp": L_t, "ndc": ndc_t, "hops": hops_t, "L_grid": curve[hit][0],
-                          "ms_at_L_grid": ms, "qps_at_L_grid": len(q) / ms * 1e3}
+                          "ms_at_L_grid": ms, "qps_at_L_grid": len(qq) / ms * 1e3}
         row = {"n": n, "knn_s": t_knn, "edge_selection_s": t_edge,
                "aod": float((g >= 0).sum().item()) / n, "at_recall": at,
                "curve": [{"L": c[0], "recall10": c[1], "ndc": c[2], "hops": c[3],
@@ -756,11 +779,12 @@ def bench_scaling(a):
             c1 = float((x * y).sum() / (x * x).sum())  # least squares through the origin
             fits[str(t)] = {"model": "ndc = c * n^(1/13) * ln n", "c": c1,
                             "rel_residuals": [float(v) for v in (y - c1 * x) / y]}
+    sets = ("prefixes of the sift-shaped synthetic 1,000,000 x 128 set" if a.scaling_mode == "prefix"
+            else "a fresh draw of the sift-shaped mixture per n with n / 1,000 components")
     return {"metric": "index build and search cost against n at fixed recall@10 (1 GPU)",
-            "workload": "prefixes of the sift-shaped synthetic 1,000,000 x 128 set, NSSG l = 100, "
-                        "R = 50, 60 degrees built on the GPU, 10,000 queries, K = 100, 3 draws of "
-                        "the 10 navigating nodes", "rows": rows, "fits": fits,
-            "data": "synthetic (seeded)"}
+            "workload": f"{sets}, NSSG l = 100, R = 50, 60 degrees built on the GPU, 10,000 queries, "
+                        "K = 100, 3 draws of the 10 navigating nodes", "mode": a.scaling_mode,
+            "rows": rows, "fits": fits, "data": "synthetic (seeded)"}
 
 
 def bench_sharded(a):

@@ -175,9 +175,10 @@ typedef struct {
     int32_t d, dtype, metric;
     const float* dim_scale;    /* DEVICE float[d] for FP8, else NULL */
     const float* base_f32;     /* DEVICE FP32 vectors for the rerank, or NULL */
-    int32_t rerank;            /* 0: none; -1: rerank the first K_i entries of
-                                  each query; > 0: max(rerank, K_i) entries
-                                  (capped at L_i) */
+    int32_t rerank;            /* 0: none; -m (1 <= m <= 16): rerank the first
+                                  m * K_i entries of each query; > 0:
+                                  max(rerank, K_i) entries (capped at L_i);
+                                  below -16: SSG_EINVAL */
     const uint32_t* graph;     /* DEVICE n x R */
     int32_t R;
     const uint32_t* entry_ids; /* DEVICE [n_entry] */

@@ -32,6 +32,8 @@ def candidate_shapes(dtype: torch.dtype, d: int, cap: int = 512):
         variants = (0, 2, 7, 8)
     elif d == 128 and dtype == torch.uint8:
         variants = (0, 3)
+    elif d == 96 and dtype == torch.bfloat16:
+        variants = (0, 4)
     out = [dict(gather_variant=v, hash_log2=h, waves_per_block=w, queries_per_wave=1)
            for v in variants for h in (0, 11) for w in (1, 2)]
     if d in (96, 128) and cap <= 256:

@@ -43,7 +43,8 @@ class BatchedSearch:
     mixed batch; ``run()`` enqueues it on the current stream.
 
     base / base_f32 / dim_scale as in ``search``; L, K: int32 [nq] (host or
-    device); rerank: 0 none, -1 the first K_i entries, > 0 a fixed count.
+    device); rerank: 0 none, -m the first m * K_i entries (1 <= m <= 16),
+    > 0 a fixed count (at least K_i).
     no_alloc: run through ssg_search_batched_noalloc (the work-queue counters
     in the library's per-device array; calls on one device must not overlap).
     shapes: {max_L bucket capacity: dict(gather_variant, hash_log2,

@@ -464,7 +464,7 @@ __device__ __forceinline__ void run_groups(const Args& a, unsigned char* wave_ld
   // cache is dead here, so its LDS holds the new keys; `stage` the order.
   if (a.base_f32 != nullptr) {
     constexpr int RL = S < 16 ? S : 16;  // lanes per candidate
-    const int rr = live ? min(a.rerank < 0 ? K : max(a.rerank, K), size) : 0;
+    const int rr = live ? min(a.rerank < 0 ? -a.rerank * K : max(a.rerank, K), size) : 0;
     uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
     const int d4 = a.d >> 2;
     const float4* q4 = reinterpret_cast<const float4*>(q);

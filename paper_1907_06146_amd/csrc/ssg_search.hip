@@ -473,7 +473,7 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
   // dead here, so its LDS holds the new keys; `stage` holds the sorted order.
   // (never fewer than K entries: every returned entry is re-scored)
   if (a.base_f32 != nullptr) {
-    const int rr = min(a.rerank < 0 ? K : max(a.rerank, K), size);
+    const int rr = min(a.rerank < 0 ? -a.rerank * K : max(a.rerank, K), size);
     uint32_t* rids = bids;  // reused 64 at a time
     uint64_t* rkeys = reinterpret_cast<uint64_t*>(table);
     const int d4 = a.d >> 2;
@@ -1230,7 +1230,7 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
                         D->out_dists);
   if (rc) return rc;
   if (D->nq > 0 && (!D->L || !D->K)) return fail(SSG_EINVAL, "per-query L and K arrays are required");
-  if (D->rerank < -1) return fail(SSG_EINVAL, "rerank must be -1, 0 or positive");
+  if (D->rerank < -16) return fail(SSG_EINVAL, "rerank must be in [-16, -1], 0 or positive");
   if (D->rerank != 0 && !D->base_f32) return fail(SSG_EINVAL, "rerank needs base_f32");
   if (D->base_f32 && reinterpret_cast<uintptr_t>(D->base_f32) % 16)
     return fail(SSG_EINVAL, "base_f32 must be 16-byte aligned");

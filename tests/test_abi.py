@@ -196,3 +196,27 @@ def test_query_lds_bytes_on_host():
     f(64, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 99)  # a bad visited size: 0, message kept
     assert f(64, 50, 128, _lib.SSG_F32, 10 ** 6, 0, 99) == 0
     assert _lib.last_error() == msg
+
+
+def _batch(rerank):
+    keep, p = _fake(1 << 14)
+    d = _lib.BatchDesc(p, 100, 32, 0, 0, None, p, rerank, p, 8, p, 2, p, 4, p, p, 10, p, p,
+                       None, None, None, 0)
+    b = (_lib.Bucket * 1)()
+    b[0] = _lib.Bucket(p, 4, 64, 0, 0, 0, 0, 0, 0)
+    return keep, p, d, b
+
+
+def test_batched_rerank_multiple_rejected_on_host():
+    """rerank = -m reranks m * K_i entries for 1 <= m <= 16; below -16 the
+    call is refused before anything reaches the device."""
+    keep, p, d, b = _batch(-17)
+    rc = _lib.lib().ssg_search_batched(ctypes.byref(d), b, 1, ctypes.c_void_p(p), 1 << 12, None)
+    assert rc == _lib.SSG_EINVAL and "rerank" in _lib.last_error()
+
+
+def test_no_alloc_entry_rejects_bucket_counts_on_host():
+    keep, p, d, b = _batch(0)
+    for nb in (0, 65):
+        assert _lib.lib().ssg_search_batched_noalloc(ctypes.byref(d), b, nb, None) == _lib.SSG_EINVAL
+        assert "64" in _lib.last_error()

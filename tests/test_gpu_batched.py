@@ -134,25 +134,26 @@ def test_bf16_rerank_batch(c4s):
     cfg, base, q, g, entry, Lq, Kq = c4s
     tb = _dev(base)
     qb, _ = quantize(tb, "bf16")
-    bs = BatchedSearch(qb, _dev(g), _dev(entry), _dev(q), Lq, Kq, "ip", base_f32=tb, rerank=-1)
-    bi, bd = (t.cpu().numpy() for t in bs.run())
-    torch.cuda.synchronize()
     deq = P.bf16_decode(qb.view(torch.int16).cpu().numpy().view(np.uint16))
     from parity_util import assert_parity, classify
-    for (L, K) in sorted(set(zip(Lq.tolist(), Kq.tolist())))[::11]:
-        rows = np.nonzero((Lq == L) & (Kq == K))[0]
-        T = 4 * L + 64
-        pi, pd, ptr = search(qb, _dev(g), _dev(entry), _dev(q[rows]), K, L, "ip", base_f32=tb,
-                             rerank_k=K, trace=T)
+    for m in (1, 3):  # rerank the first m * K_i entries of each query
+        bs = BatchedSearch(qb, _dev(g), _dev(entry), _dev(q), Lq, Kq, "ip", base_f32=tb, rerank=-m)
+        bi, bd = (t.cpu().numpy() for t in bs.run())
         torch.cuda.synchronize()
-        pi = pi.cpu().numpy()
-        assert np.array_equal(pi, bi[rows, :K])  # the batched form equals the plain search
-        oi, od = P.search_precision(base, deq, g, entry, q[rows], K, L, "ip", rerank=K)
-        otr = core.search(deq, g, entry, q[rows], K, L, "ip", trace=T)[4]
-        rr = classify(base, q[rows], pi.view(np.uint32), oi, "ip", 1e-5, ptr.cpu().numpy(), otr,
-                      search_base=deq)
-        assert_parity(rr, 0.99, f"bf16 rerank L={L} K={K}")
-    bs.close()
+        for (L, K) in sorted(set(zip(Lq.tolist(), Kq.tolist())))[::11]:
+            rows = np.nonzero((Lq == L) & (Kq == K))[0]
+            T = 4 * L + 64
+            pi, pd, ptr = search(qb, _dev(g), _dev(entry), _dev(q[rows]), K, L, "ip", base_f32=tb,
+                                 rerank_k=m * K, trace=T)
+            torch.cuda.synchronize()
+            pi = pi.cpu().numpy()
+            assert np.array_equal(pi, bi[rows, :K])  # the batched form equals the plain search
+            oi, od = P.search_precision(base, deq, g, entry, q[rows], K, L, "ip", rerank=m * K)
+            otr = core.search(deq, g, entry, q[rows], K, L, "ip", trace=T)[4]
+            rr = classify(base, q[rows], pi.view(np.uint32), oi, "ip", 1e-5, ptr.cpu().numpy(), otr,
+                          search_base=deq)
+            assert_parity(rr, 0.99, f"bf16 rerank {m} x K, L={L} K={K}")
+        bs.close()
 
 
 def test_autotuner_picks_valid_shapes(c4s, tmp_path):
