@@ -934,9 +934,10 @@ def bench_build(a):
 def bench_precision_c3(a):
     """GIST-shaped 1M x 960 workload (values in [0, 1], squared L2), 1,000
     queries, K = 10: FP32, BF16 and FP8-E4M3 storage (FP32 accumulation),
-    each with and without an FP32 rerank of the whole pool, at every swept
-    pool size: throughput, recall@10 and the error of the returned distances
-    against FP64 recomputation."""
+    each without rerank, with an FP32 rerank of the returned K and of the
+    whole pool, at every swept pool size: throughput, recall@10 and the error
+    of the returned distances against FP64 recomputation. Then the 16,000
+    steady-state queries (distinct, with their own exact top 10) at L = 200."""
     import torch
 
     from paper_1907_06146_amd import graph_io, quantize, search
@@ -970,11 +971,11 @@ def bench_precision_c3(a):
     rows = []
     for L in sorted(orc):
         for fmt in ("fp32", "bf16", "fp8"):
-            for rr in ((False,) if fmt == "fp32" else (False, True)):
+            for rr in ((0,) if fmt == "fp32" else (0, K, L)):
                 cb, sc = codes[fmt]
                 kw = dict(dim_scale=sc)
                 if rr:
-                    kw.update(base_f32=tb, rerank_k=L)
+                    kw.update(base_f32=tb, rerank_k=rr)
                 ids, dd, ndc, hops = search(cb, tg, te, tq, K, L, stats=True, **kw)
                 torch.cuda.synchronize()
                 ids_h = ids.cpu().numpy()
@@ -983,8 +984,8 @@ def bench_precision_c3(a):
                 ndc_m = ndc.double().mean().item()
                 hops_m = hops.double().mean().item()
                 bq = moved_bytes(ndc_m, hops_m, d, tg.shape[1], cfg["s"], K, elem[fmt]) \
-                    + (L * d * 4 if rr else 0)
-                row = {"L": L, "form": fmt + ("+fp32 rerank" if rr else ""),
+                    + min(rr, L) * d * 4
+                row = {"L": L, "form": fmt + (f"+fp32 rerank of {min(rr, L)}" if rr else ""),
                        "recall10": recall_at(ids_h, gt, 10), "oracle_recall10": orc[L]["recall10"],
                        "ms": ms, "qps": nq / ms * 1e3, "ndc": ndc_m, "hops": hops_m,
                        "moved_bytes_per_query": bq, "moved_GBps": bq * nq / (ms / 1e3) / 1e9,
@@ -995,15 +996,22 @@ def bench_precision_c3(a):
     import synth
     steady = {}
     tq16 = torch.from_numpy(synth.steady_queries(cfg)).to(dev)
+    sgt = np.load(os.path.join(graph_io.default_root(), "c3", "steady_gt_ids.npy"), allow_pickle=False)
     Ls = 200
-    for fmt in ("fp32", "bf16", "fp8"):
+    for fmt, rr in (("fp32", 0), ("bf16", K), ("fp8", K), ("bf16", Ls), ("fp8", Ls)):
         cb, sc = codes[fmt]
         kw = dict(dim_scale=sc)
-        if fmt != "fp32":
-            kw.update(base_f32=tb, rerank_k=Ls)
+        if rr:
+            kw.update(base_f32=tb, rerank_k=rr)
         ms = _time(lambda: search(cb, tg, te, tq16, K, Ls, **kw), max(3, a.steps // 2), 1, stream)
-        steady[fmt] = {"L": Ls, "queries": int(tq16.shape[0]), "ms": ms, "qps": tq16.shape[0] / ms * 1e3}
-        log(f"steady {fmt}: {steady[fmt]}")
+        ids, _ = search(cb, tg, te, tq16, K, Ls, **kw)
+        torch.cuda.synchronize()
+        name = fmt + (f"+fp32 rerank of {rr}" if rr else "")
+        steady[name] = {"L": Ls, "queries": int(tq16.shape[0]), "ms": ms, "qps": tq16.shape[0] / ms * 1e3,
+                        "recall10": recall_at(ids.cpu().numpy(), sgt, 10)}
+        log(f"steady {name}: {steady[name]}")
+    for name, v in steady.items():
+        v["speedup_vs_fp32"] = steady["fp32"]["ms"] / v["ms"]
     return {"metric": "queries/s and recall@10 per storage precision (GIST-shaped 1M x 960, 1 GPU)",
             "unit": "queries/s", "n_gpus": 1, "workload": "gist-shaped synthetic 1,000,000 x 960 in "
             "[0, 1], 1,000 queries, K = 10, squared L2", "rows": rows, "steady_state_16k_distinct": steady,
