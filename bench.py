@@ -1092,10 +1092,12 @@ def bench_serving(a):
             "unit": "queries/s", "n_gpus": 1, **s}
 
 def bench_shapes(a):
-    """Launch-shape sweep of the headline search (1M x 128, L = 80): gather
-    variant x visited-set size x waves per workgroup, FP32 and BF16 storage,
-    on the 10,000 queries and on them tiled 10 times. Every row's ids are
-    checked against the oracle's stored result."""
+    """Launch-shape sweep of the headline search (1M x 128, L = 80, K = 100):
+    gather variant x visited-cache size x waves per workgroup for FP32, BF16
+    and FP8 storage (no rerank: the search's own shape), on the 10,000
+    queries and on the 100,000 distinct steady-state queries. FP32 and BF16
+    (lossless on these integers) rows are checked against the oracle's ids;
+    FP8 rows report recall@10."""
     import torch
     import synth
     from paper_1907_06146_amd import graph_io, search, quantize
@@ -1110,26 +1112,34 @@ def bench_shapes(a):
         L = a.L or json.load(f)["L_op"]
     K = cfg["K"]
     oi = np.load(os.path.join(droot, f"oracle_L{L}_ids.npy"), allow_pickle=False)
+    gt = np.load(os.path.join(droot, "gt_ids.npy"), allow_pickle=False)
     dev = torch.device("cuda:0")
     tb = torch.from_numpy(base).to(dev)
     tg = graph_io.to_device(gc["graph"], dev)
     te = graph_io.to_device(gc["entry_ids"], dev)
-    qb, _ = quantize(tb, "bf16")
+    forms = {"f32": (tb, None), "bf16": quantize(tb, "bf16"), "fp8": quantize(tb, "fp8")}
     stream = torch.cuda.current_stream(dev)
-    plan = [("f32", v, hl, w) for v in (0, 1, 2, 3, 4, 6) for hl in (11, 12) for w in (1, 2)]
-    plan += [("bf16", 0, hl, w) for hl in (11, 12) for w in (1, 2)]
+    variants = {"f32": (0, 1, 2, 3, 4, 6), "bf16": (0, 2, 3, 4, 7, 8), "fp8": (0, 1, 2, 3)}
+    plan = [(dt, v, hl, w) for dt in ("f32", "bf16", "fp8") for v in variants[dt]
+            for hl in (11, 12) for w in (1, 2)]
     rows = []
-    for tile in (1, 10):
-        tq = torch.from_numpy(np.tile(q, (tile, 1))).to(dev)
+    sets = (("headline", torch.from_numpy(q).to(dev)),
+            ("steady", torch.from_numpy(synth.steady_queries(cfg)).to(dev)))
+    for name, tq in sets:
         ids = torch.empty((len(tq), K), dtype=torch.int32, device=dev)
         dd = torch.empty((len(tq), K), dtype=torch.float32, device=dev)
         for dt, var, hl, wpb in plan:
-            kw = dict(out=(ids, dd), gather_variant=var, hash_log2=hl, waves_per_block=wpb)
-            bse = tb if dt == "f32" else qb
-            ms = _time(lambda: search(bse, tg, te, tq, K, L, **kw), 10 if tile == 1 else 3, 2, stream)
-            same = bool(np.array_equal(ids[:len(q)].cpu().numpy().view(np.uint32), oi))
-            r = dict(queries=len(tq), dtype=dt, variant=var, hash_log2=hl, waves_per_block=wpb,
-                     ms=ms, qps=len(tq) / ms * 1e3, ids_equal_oracle=same)
+            bse, sc = forms[dt]
+            kw = dict(out=(ids, dd), gather_variant=var, hash_log2=hl, waves_per_block=wpb, dim_scale=sc)
+            ms = _time(lambda: search(bse, tg, te, tq, K, L, **kw), 10 if name == "headline" else 3, 2, stream)
+            r = dict(queries=len(tq), set=name, dtype=dt, variant=var, hash_log2=hl, waves_per_block=wpb,
+                     ms=ms, qps=len(tq) / ms * 1e3)
+            if name == "headline":
+                got = ids.cpu().numpy()
+                if dt == "fp8":
+                    r["recall10"] = recall_at(got, gt, 10)
+                else:
+                    r["ids_equal_oracle"] = bool(np.array_equal(got.view(np.uint32), oi))
             log(f"shapes: {r}")
             rows.append(r)
     return {"metric": "launch-shape sweep of the 1M x 128 search (L = %d, K = %d)" % (L, K),
