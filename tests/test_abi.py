@@ -96,13 +96,20 @@ def test_validate_graph():
     assert _validate([[1, 3, S], [0, S, S], [0, 1, S]]) == _lib.SSG_EINVAL  # id >= n
 
 
-def test_validate_cached_graphs():
-    from oracle import cache
-    for name in ("c1", "c2s"):
-        if not cache.exists(name, "graph"):
-            pytest.skip("graph cache not built")
-        g = cache.load(name, "graph")
-        assert _validate(g) == 0
+def test_validate_oracle_graphs():
+    """Graphs the oracle builds meet the search's preconditions: a small
+    NSSG built here, and every stored full-size graph that is present."""
+    import synth
+    from oracle import cache, core
+    cfg = dict(synth.CONFIGS["c2s"], n=3000)
+    base = synth.base_vectors(cfg)
+    entry = synth.entry_choice(cfg)
+    knn, _ = core.knn_graph(base, 40)
+    g = core.nssg_build(base, knn, 60, 32, 60.0, entry)["graph"]
+    assert _validate(g) == 0
+    for name in ("c2", "c3", "c4"):
+        if cache.exists(name, "graph"):
+            assert _validate(cache.load(name, "graph")) == 0, name
 
 
 @pytest.mark.parametrize("n,d,K", [(1, 8, 1), (100, 0, 5), (100, 8, 0), (100, 8, 101), (10, 8, 10),
