@@ -206,7 +206,13 @@ typedef struct {
     int32_t gather_variant;    /* launch shape (see ssg_search_opts); 0 = default */
     int32_t hash_log2;         /* 0 = default */
     int32_t waves_per_block;   /* 0 = default */
-    int32_t blocks;            /* persistent grid size; 0 = fill the GPU once */
+    int32_t blocks;            /* 0: one wavefront per listed query (the
+                                  hardware starts the next query as a
+                                  search ends); > 0: a persistent grid of
+                                  that many workgroups taking queries from
+                                  the bucket's work-queue counter (two
+                                  queries per wavefront always run
+                                  persistent, filling the GPU once) */
     int32_t visited_kind;      /* visited-set form, as ssg_search_opts.visited_kind
                                   (0 default, 1 hash, 2 tag cache) */
     int32_t queries_per_wave;  /* as ssg_search_opts.queries_per_wave (bucket

@@ -598,9 +598,9 @@ __device__ __forceinline__ void run_query(const Args& a, unsigned char* my, cons
   wave_sync();  // LDS of this wave is reused by its next query
 }
 
-// One query per wavefront (counter == null), or persistent: every wavefront
-// takes the next slot of the work queue until the queue is exhausted (each
-// wavefront exits once its fetched slot is past the end).
+// One query per wavefront: query `slot` with the launch's L and K, or, with
+// a query list (one L bucket of the batched form), query qlist[slot] with its
+// own L_i and K_i clamped to the launch's pool capacity and row stride.
 template <typename T, int DC, int G, int NP, int PREG, bool QL>
 __global__ __launch_bounds__(256) void search_kernel(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -608,10 +608,23 @@ __global__ __launch_bounds__(256) void search_kernel(Args a) {
   const int wv = threadIdx.x >> 6;
   unsigned char* my = smem + (size_t)wv * a.lds_per_wave;
   const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
-  if (slot >= a.nq) return;  // uniform per wavefront
-  run_query<T, DC, G, NP, PREG, QL>(a, my, lane, slot, a.L, a.K);
+  int64_t qid = slot;
+  int L = a.L, K = a.K;
+  if (a.qlist) {
+    if (slot >= a.nlist) return;  // uniform per wavefront
+    qid = (int64_t)__builtin_amdgcn_readfirstlane((int)a.qlist[slot]);
+    if (qid < 0 || qid >= a.nq) return;  // a bad list entry is skipped, never dereferenced
+    L = __builtin_amdgcn_readfirstlane(min(max(a.L_arr ? a.L_arr[qid] : a.L, 1), 64 * PREG));
+    K = __builtin_amdgcn_readfirstlane(min(max(a.K_arr ? a.K_arr[qid] : a.K, 1), a.kstride));
+  } else if (slot >= a.nq) {
+    return;
+  }
+  run_query<T, DC, G, NP, PREG, QL>(a, my, lane, qid, L, K);
 }
 
+// Persistent: every wavefront takes the next slot of the bucket's work queue
+// until the queue is exhausted (each wavefront exits once its fetched slot is
+// past the end).
 template <typename T, int DC, int G, int NP, int PREG, bool QL>
 __global__ __launch_bounds__(256) void search_kernel_batched(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -626,11 +639,11 @@ __global__ __launch_bounds__(256) void search_kernel_batched(Args a) {
       slot = (int64_t)__builtin_amdgcn_readfirstlane(s0);
     }
     if (slot >= a.nlist) break;  // uniform per wavefront
-    const int64_t qid = a.qlist ? (int64_t)a.qlist[slot] : slot;
+    const int64_t qid = a.qlist ? (int64_t)__builtin_amdgcn_readfirstlane((int)a.qlist[slot]) : slot;
     if (qid >= 0 && qid < a.nq) {  // a bad queue entry is skipped, never dereferenced
       // per-query sizes are clamped to this launch's pool capacity and row stride
-      const int L = min(max(a.L_arr ? a.L_arr[qid] : a.L, 1), 64 * PREG);
-      const int K = min(max(a.K_arr ? a.K_arr[qid] : a.K, 1), a.kstride);
+      const int L = __builtin_amdgcn_readfirstlane(min(max(a.L_arr ? a.L_arr[qid] : a.L, 1), 64 * PREG));
+      const int K = __builtin_amdgcn_readfirstlane(min(max(a.K_arr ? a.K_arr[qid] : a.K, 1), a.kstride));
       run_query<T, DC, G, NP, PREG, QL>(a, my, lane, qid, L, K);
     }
     if (!a.counter) break;
@@ -1249,7 +1262,11 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
     if (b.waves_per_block < 0 || b.waves_per_block > 4 || b.blocks < 0)
       return fail(SSG_EINVAL, "bucket %d: bad launch shape", i);
     const int preg = preg_for(b.max_L);
-    Launch lc = pick_launch(D->dtype, dc, preg, b.gather_variant, true);
+    // blocks == 0: one wavefront per listed query (the plain kernel reading
+    // the list; the hardware starts the next query as a search ends); > 0: a
+    // persistent grid of that many workgroups pulling from the work queue
+    const bool per_query = b.blocks == 0;
+    Launch lc = pick_launch(D->dtype, dc, preg, b.gather_variant, !per_query);
     BucketLaunch bl{};
     Args& a = bl.a;
     if (b.visited_kind < 0 || b.visited_kind > 2)
@@ -1313,8 +1330,9 @@ int prepare_batched(const ssg_batch_desc* D, const ssg_bucket* B, int nb, void* 
                                                      (int)bl.threads, bl.lds) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    int64_t want = b.blocks > 0 ? b.blocks : (int64_t)per_cu * cus;
     const int64_t need = (b.count + (int64_t)wpb * qpw - 1) / ((int64_t)wpb * qpw);
+    int64_t want = b.blocks > 0 ? b.blocks : (int64_t)per_cu * cus;
+    if (per_query && qpw == 1) want = need;
     bl.blocks = (unsigned)std::max<int64_t>(1, std::min(want, std::max<int64_t>(need, 1)));
     out[i] = bl;
   }

@@ -128,6 +128,28 @@ def test_each_query_equals_its_plain_launch(c4s):
     bs.close()
 
 
+@pytest.mark.parametrize("blocks", [1, 7, 512])
+def test_persistent_grid_equals_one_wave_per_query(c4s, blocks):
+    """A persistent grid of any size (work-queue counter per bucket) gives
+    the same rows as one wavefront per listed query, graph-captured too."""
+    from paper_1907_06146_amd.batched import BatchedSearch
+    cfg, base, q, g, entry, Lq, Kq = c4s
+    args = (_dev(base), _dev(g), _dev(entry), _dev(q), Lq, Kq, "ip")
+    ref = BatchedSearch(*args, use_graph=False, stats=True)
+    ri, rd = (t.cpu().numpy() for t in ref.run())
+    rh = ref.hops.cpu().numpy()
+    shapes = {cap: {"blocks": blocks} for cap in (64, 128, 256, 512)}
+    for use_graph in (False, True):
+        bs = BatchedSearch(*args, shapes=shapes, use_graph=use_graph, stats=True)
+        for _ in range(2):  # a replay starts from reset counters
+            bi, bd = (t.cpu().numpy() for t in bs.run())
+            torch.cuda.synchronize()
+            assert np.array_equal(bi, ri) and np.array_equal(bd, rd)
+            assert np.array_equal(bs.hops.cpu().numpy(), rh)
+        bs.close()
+    ref.close()
+
+
 def test_bf16_rerank_batch(c4s):
     from paper_1907_06146_amd import quantize, search
     from paper_1907_06146_amd.batched import BatchedSearch

@@ -33,9 +33,12 @@ def index():
     return base, q, g, entry
 
 
-def _pair(index, nq, L_choices, seed, dtype="f32"):
+def _pair(index, nq, L_choices, seed, dtype="f32", persistent=False):
     """Two BatchedSearch objects over the same queries: the workspace form
-    and the no-allocation form (each with its own output buffers)."""
+    and the no-allocation form (each with its own output buffers); with
+    persistent=True every bucket runs as a persistent grid taking queries
+    from its work-queue counter (the counters the no-allocation form keeps in
+    its own array)."""
     from paper_1907_06146_amd import quantize
     from paper_1907_06146_amd.batched import BatchedSearch
     base, q, g, entry = index
@@ -49,15 +52,17 @@ def _pair(index, nq, L_choices, seed, dtype="f32"):
         bse, _ = quantize(tb, "bf16")
         kw = dict(base_f32=tb, rerank=-1)
     args = (bse, _dev(g), _dev(entry), _dev(q[:nq]), Lq, Kq, "ip")
+    if persistent:
+        kw["shapes"] = {cap: {"blocks": 96} for cap in (64, 128, 256, 512)}
     ref = BatchedSearch(*args, use_graph=False, stats=True, **kw)
     new = BatchedSearch(*args, use_graph=False, stats=True, no_alloc=True, **kw)
     return ref, new
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_no_alloc_equals_workspace_form(index, dtype):
-    big = _pair(index, 1500, np.arange(16, 513, 16), 1, dtype)   # all four buckets
-    small = _pair(index, 300, np.arange(16, 129, 16), 2, dtype)  # two buckets, fewer queries
+@pytest.mark.parametrize("dtype,persistent", [("f32", True), ("bf16", True), ("f32", False)])
+def test_no_alloc_equals_workspace_form(index, dtype, persistent):
+    big = _pair(index, 1500, np.arange(16, 513, 16), 1, dtype, persistent)   # all four buckets
+    small = _pair(index, 300, np.arange(16, 129, 16), 2, dtype, persistent)  # two buckets, fewer queries
     assert len(big[1].plan) == 4 and len(small[1].plan) == 2
     for ref, new in (big, small):  # two calls in a row, the second smaller
         ref.run()
@@ -67,7 +72,7 @@ def test_no_alloc_equals_workspace_form(index, dtype):
         assert torch.equal(ref.out_d, new.out_d)
         assert torch.equal(ref.hops, new.hops)
     # the first call's outputs are not disturbed by the second
-    again = _pair(index, 1500, np.arange(16, 513, 16), 1, dtype)[1]
+    again = _pair(index, 1500, np.arange(16, 513, 16), 1, dtype, persistent)[1]
     again.run()
     torch.cuda.synchronize()
     assert torch.equal(again.out_ids, big[0].out_ids)
