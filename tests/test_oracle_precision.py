@@ -6,7 +6,6 @@ a binary32, so the integers 0..256 are exact (8 significant bits).
 """
 
 import numpy as np
-import pytest
 
 from oracle import core, precision as P
 
