@@ -489,8 +489,8 @@ def _load(name):
 def bench_batched(a):
     """Deep-shaped 1M x 96 unit-norm workload, inner product, 100,000 queries
     with their own L in {16..512} and K in {1, 10, 100}: the plain FP32 search
-    launched once per (L, K) group, against one graph-captured persistent
-    batched launch (FP32, and BF16 with an FP32 rerank of each query's K)."""
+    launched once per (L, K) group, against one graph-captured batched
+    launch (FP32, and BF16 with an FP32 rerank of each query's K)."""
     import torch
 
     import synth

@@ -15,8 +15,9 @@ Two ways to put requests on the device:
   per-slot streams;
 * ``BatchScheduler`` + ``GpuBatchDevice`` (continuous batching): whenever a
   batch slot is free, the waiting requests that fit the device budget (FIFO)
-  are launched together as one mixed batch through the persistent batched
-  kernel, each query with its own request's pool size L and result count K.
+  are launched together as one mixed batch through the batched entry point
+  (``ssg_search_batched``: one launch per L bucket, one wavefront per query),
+  each query with its own request's pool size L and result count K.
   This keeps the device full with a few launches at a time instead of one
   launch per request.
 
@@ -393,7 +394,7 @@ class GpuDevice:
 class GpuBatchDevice:
     """Batch slots for ``BatchScheduler``: each slot owns a stream, pinned
     staging buffers and device buffers for up to ``max_batch`` queries, and
-    runs a batch through the persistent batched kernel (``ssg_search_batched``)
+    runs a batch through the batched entry point (``ssg_search_batched``)
     with every query's own L and K; nothing is allocated per batch."""
 
     def __init__(self, base, graph, entry_ids, n_slots: int, max_batch: int, max_K: int,
