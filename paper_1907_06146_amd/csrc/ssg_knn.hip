@@ -88,6 +88,19 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
   uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
 }
+// Global-memory views of workspace pointers. The pointers reach the kernels
+// inside argument structs, so the compiler cannot tell their address space
+// and would emit flat accesses, which count against the LDS wait counter as
+// well: every LDS wait would then also wait for the tile prefetch.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -246,7 +259,7 @@ struct ScanSmem {
 // Merges every wavefront's queue segment into the per-row candidate lists;
 // called by all threads. Leaves the segments empty.
 template <class SM>
-__device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
+__device__ void merge_queue(SM& sm, uint64_t* lists, int KP, int64_t r0) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int t = tid; t < BM; t += NT) { sm.rowcnt[t] = 0; sm.rowfill[t] = 0; }
   __syncthreads();
@@ -272,7 +285,6 @@ __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
     sm.mg.q2[sm.rowoff[r] + atomicAdd(&sm.rowfill[r], 1u)] = v;
   }
   __syncthreads();
-  const int KP = a.KP;
   uint64_t* Lk = sm.mg.mt[wave];
   uint64_t* Ok = Lk + KP_MAX;
   uint64_t* Nk = Lk + 2 * KP_MAX;
@@ -281,7 +293,7 @@ __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
   auto fetch = [&](int r) {
     if (r >= BM) return;
     const uint32_t lc = sm.lcnt[r];
-    const uint64_t* gl = a.w.lists + (r0 + r) * KP_MAX;
+    const auto gl = gmem(lists + (r0 + r) * KP_MAX);
     if ((uint32_t)lane < lc) pre0 = gl[lane];
     if ((uint32_t)lane + 64 < lc) pre1 = gl[lane + 64];
   };
@@ -294,7 +306,7 @@ __device__ void merge_queue(SM& sm, const ScanArgs& a, int64_t r0) {
     fetch(r + NW);
     if (cnt == 0) continue;
     const uint32_t off = sm.rowoff[r];
-    uint64_t* gl = a.w.lists + (r0 + r) * KP_MAX;
+    const auto gl = gmem(lists + (r0 + r) * KP_MAX);
     wave_sync();
     for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
       const uint32_t m = min(64u, cnt - c0);
@@ -349,7 +361,15 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
   const int64_t r0 = (int64_t)blockIdx.x * BM;
   const int nchunk = AREG ? 1 : DP / KC;
   const int64_t ntiles = (n + BN - 1) / BN;
-  const uint16_t* xs[2] = {a.w.xh, a.w.xl};
+  // the argument block's fields as plain values: a reference to the block
+  // (lambdas, helper calls) would make the compiler keep a private copy of it
+  const uint16_t* const xh = a.w.xh;
+  const uint16_t* const xl = a.w.xl;
+  const float* const nyp = a.w.ny;
+  uint64_t* const lists = a.w.lists;
+  uint32_t* const lcntp = a.w.lcnt;
+  const int KP = a.KP;
+  auto xs = [=](int h) { return h ? xl : xh; };
   uint64_t* qseg = sm.q + wave * QW;
 
   for (int t = tid; t < BM; t += NT) {
@@ -369,35 +389,43 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
           const int64_t row = r0 + 64 * wm + 16 * bi + (lane & 15);
-          areg[h][bi][ks] = *reinterpret_cast<const bf16x8*>(xs[h] + row * DP + 32 * ks + 8 * (lane >> 4));
+          areg[h][bi][ks] = *reinterpret_cast<const bf16x8*>(xs(h) + row * DP + 32 * ks + 8 * (lane >> 4));
         }
   }
 
   // staged-operand registers (the next chunk is loaded while this one is used)
   constexpr int CPA = AREG ? 1 : BM * KC / 8 / NT;  // A pieces per thread (staged path)
+  constexpr int PPR = KC / 8;                        // 16-byte pieces per row of a chunk
+  constexpr int RPC = NT / PPR;                      // rows between a thread's pieces
+  static_assert(NT % PPR == 0, "pieces of a chunk row split evenly over the threads");
+  // piece c of this thread: row tid / PPR + c * RPC, 16-byte column tid % PPR
+  const uint32_t boff = (uint32_t)((tid / PPR) * DP + (tid % PPR) * 8) * 2u;  // bytes
+  const uint32_t bstep = (uint32_t)RPC * (uint32_t)DP * 2u;
+  const int soff = (tid / PPR) * SS + (tid % PPR) * 8;                       // LDS elements
   u32x4 pb[NB][CPT];
   u32x4 pa[AREG ? 1 : NB][CPA];
   float nyn[BJ];  // squared norms of the prefetched tile's columns
   auto load_chunk = [&](int64_t tile, int chunk) {
     const int kc = chunk * KC;
     if (chunk == 0) {
+      const auto nyt = gmem(nyp + tile * BN + 32 * wn + (lane & 15));
 #pragma unroll
-      for (int bj = 0; bj < BJ; ++bj) nyn[bj] = a.w.ny[tile * BN + 32 * wn + 16 * bj + (lane & 15)];
+      for (int bj = 0; bj < BJ; ++bj) nyn[bj] = nyt[16 * bj];
     }
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
+      const char* tb = reinterpret_cast<const char*>(xs(h) + tile * BN * DP + kc);
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int piece = tid + c * NT;
-        const int rr = piece / (KC / 8), part = piece % (KC / 8);
-        pb[h][c] = *reinterpret_cast<const u32x4*>(xs[h] + (tile * BN + rr) * DP + kc + part * 8);
+      for (int c = 0; c < CPT; ++c) {  // uniform base per piece, one per-thread offset
+        const char* tbc = tb + (size_t)c * bstep;
+        pb[h][c] = *gmem(reinterpret_cast<const u32x4*>(tbc + boff));
       }
       if constexpr (!AREG) {
+        const char* ta = reinterpret_cast<const char*>(xs(h) + r0 * DP + kc);
 #pragma unroll
         for (int c = 0; c < CPA; ++c) {
-          const int piece = tid + c * NT;
-          const int rr = piece / (KC / 8), part = piece % (KC / 8);
-          pa[h][c] = *reinterpret_cast<const u32x4*>(xs[h] + (r0 + rr) * DP + kc + part * 8);
+          const char* tac = ta + (size_t)c * bstep;
+          pa[h][c] = *gmem(reinterpret_cast<const u32x4*>(tac + boff));
         }
       }
     }
@@ -406,18 +434,12 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int piece = tid + c * NT;
-        const int rr = piece / (KC / 8), part = piece % (KC / 8);
-        *reinterpret_cast<u32x4*>(&sm.st.sB[h][rr * SS + part * 8]) = pb[h][c];
-      }
+      for (int c = 0; c < CPT; ++c)
+        *reinterpret_cast<u32x4*>(&sm.st.sB[h][soff + c * RPC * SS]) = pb[h][c];
       if constexpr (!AREG) {
 #pragma unroll
-        for (int c = 0; c < CPA; ++c) {
-          const int piece = tid + c * NT;
-          const int rr = piece / (KC / 8), part = piece % (KC / 8);
-          *reinterpret_cast<u32x4*>(&sm.st.sA[h][rr * SS + part * 8]) = pa[h][c];
-        }
+        for (int c = 0; c < CPA; ++c)
+          *reinterpret_cast<u32x4*>(&sm.st.sA[h][soff + c * RPC * SS]) = pa[h][c];
       }
     }
   };
@@ -492,9 +514,20 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
     // Appends the selected elements that pass the threshold; returns those
     // that found the segment full. SPECIAL tiles also drop self pairs and
     // absent columns; SEL restricts the test to the elements set in sel.
+    // Per-tile forms of the row and column codes, so that no per-element
+    // constant is live across the tile loop: element (bi, bj, i) of this lane
+    // is row rbase + 16 bi + i, column cbase + 16 bj; its queue code is
+    // kb[bj] + ((16 bi + i) << 25) and it is a self pair iff
+    // db[bj] == 16 bi + i.
     const uint32_t rbase = (uint32_t)(64 * wm + 4 * (lane >> 4));
     const uint32_t cbase = (uint32_t)(c0 + 32 * wn + (lane & 15));
-    const uint32_t n32 = (uint32_t)n, r032 = (uint32_t)r0;
+    const uint32_t n32 = (uint32_t)n;
+    uint32_t kb[BJ], db[BJ];
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      kb[bj] = (rbase << 25) | (cbase + 16 * bj);
+      db[bj] = cbase + 16 * bj - (uint32_t)r0 - rbase;
+    }
     auto push = [&](auto special_c, auto sel_c, uint64_t sel) -> uint64_t {
       constexpr bool SPECIAL = decltype(special_c)::value;
       constexpr bool SEL = decltype(sel_c)::value;
@@ -522,15 +555,14 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
             const float s = fmaf(-2.f, acc[bi][bj][i], nyc[bj]);
             bool surv = s <= tr[bi * 4 + i];
             if constexpr (SEL) surv = surv && ((sel >> e) & 1ull);
-            const uint32_t rl = rbase + 16 * bi + i;
-            const uint32_t col = cbase + 16 * bj;
-            if constexpr (SPECIAL) surv = surv && col < n32 && col != r032 + rl;
+            if constexpr (SPECIAL)
+              surv = surv && cbase + 16 * bj < n32 && db[bj] != (uint32_t)(16 * bi + i);
             const uint64_t m = __ballot(surv);
             if (m) {
               const uint32_t pos = qn + mbcnt64(m);
               if (surv) {
                 if (pos < (uint32_t)QW)
-                  qseg[pos] = ((uint64_t)ord_f32(s) << 32) | ((uint64_t)rl << 25) | col;
+                  qseg[pos] = ((uint64_t)ord_f32(s) << 32) | (kb[bj] + ((uint32_t)(16 * bi + i) << 25));
                 else
                   left |= 1ull << e;
               }
@@ -551,7 +583,7 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
     }
     __syncthreads();
     while (sm.flag) {
-      merge_queue(sm, a, r0);  // ends with a barrier; empties the segments
+      merge_queue(sm, lists, KP, r0);  // ends with a barrier; empties the segments
       qn = 0;
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
@@ -570,9 +602,9 @@ __global__ __launch_bounds__(NT, 2) void knn_scan(ScanArgs a) {
   }
   bool any = false;  // segments were published before the last barrier
   for (int w = 0; w < NW; ++w) any |= sm.qn[w] > 0;
-  if (any) merge_queue(sm, a, r0);
+  if (any) merge_queue(sm, lists, KP, r0);
   __syncthreads();
-  for (int t = tid; t < BM; t += NT) a.w.lcnt[r0 + t] = sm.lcnt[t];
+  for (int t = tid; t < BM; t += NT) gmem(lcntp)[r0 + t] = sm.lcnt[t];
 }
 
 // ---------------------------------------------------------------- rerank
