@@ -189,31 +189,45 @@ __global__ void knn_clear_flags(uint32_t* flags) {
   if (threadIdx.x < 16) flags[threadIdx.x] = 0u;
 }
 
-// One wavefront per (padded) row.
+// One wavefront per PREP_ROWS consecutive (padded) rows. The largest norm and
+// the non-integer flag are reduced over a wavefront's rows before the one
+// atomic update each (an atomic per row would serialise a million updates on
+// one word).
+constexpr int PREP_ROWS = 32;
+
 __global__ __launch_bounds__(256) void knn_prep(const float* __restrict__ base, int64_t n, int d,
                                                 int DP, int64_t NP, Ws w) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= NP) return;
-  double ss = 0.0;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * PREP_ROWS;
+  if (row0 >= NP) return;
+  const auto src = gmem(base);
+  const auto xh = gmem(w.xh), xl = gmem(w.xl);
+  uint32_t maxbits = 0;
   bool nonint = false;
-  for (int j = lane; j < DP; j += 64) {
-    const bool in = row < n && j < d;
-    const float x = in ? base[row * d + j] : 0.f;
-    const uint16_t h = bf16_rne(x);
-    const uint16_t l = bf16_rne(x - bf16_f32(h));  // x - h is exact
-    w.xh[row * DP + j] = h;
-    w.xl[row * DP + j] = l;
-    ss += (double)x * (double)x;
-    nonint |= in && !(x >= 0.f && x <= 255.f && rintf(x) == x);
+  const int64_t row1 = row0 + PREP_ROWS < NP ? row0 + PREP_ROWS : NP;
+  for (int64_t row = row0; row < row1; ++row) {
+    double ss = 0.0;
+    for (int j = lane; j < DP; j += 64) {
+      const bool in = row < n && j < d;
+      const float x = in ? src[row * d + j] : 0.f;
+      const uint16_t h = bf16_rne(x);
+      const uint16_t l = bf16_rne(x - bf16_f32(h));  // x - h is exact
+      xh[row * DP + j] = h;
+      xl[row * DP + j] = l;
+      ss += (double)x * (double)x;
+      nonint |= in && !(x >= 0.f && x <= 255.f && rintf(x) == x);
+    }
+    for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (lane == 0) {
+      const float nr = (float)sqrt(ss);
+      gmem(w.ny)[row] = (float)ss;
+      gmem(w.nrm)[row] = nr;
+      if (row < n) maxbits = max(maxbits, __float_as_uint(nr));  // non-negative floats order like their bits
+    }
   }
-  for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
   const uint64_t bad = __ballot(nonint);
   if (lane == 0) {
-    const float nr = (float)sqrt(ss);
-    w.ny[row] = (float)ss;
-    w.nrm[row] = nr;
-    if (row < n) atomicMax(&w.flags[1], __float_as_uint(nr));  // non-negative floats order like their bits
+    atomicMax(&w.flags[1], maxbits);
     if (bad) atomicOr(&w.flags[0], 1u);
   }
 }
@@ -771,7 +785,9 @@ int ssg_knn_graph(const float* base, int64_t n, int32_t d, int32_t K, uint32_t* 
   const Ws w = bind(workspace, L);
 
   hipLaunchKernelGGL(knn_clear_flags, dim3(1), dim3(64), 0, s, w.flags);
-  hipLaunchKernelGGL(knn_prep, dim3((unsigned)(L.NP / 4)), dim3(256), 0, s, base, n, d, L.DP, L.NP, w);
+  const int64_t prep_waves = (L.NP + PREP_ROWS - 1) / PREP_ROWS;
+  hipLaunchKernelGGL(knn_prep, dim3((unsigned)((prep_waves + 3) / 4)), dim3(256), 0, s, base, n, d, L.DP, L.NP,
+                     w);
   uint32_t flags[4];
   if (hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
