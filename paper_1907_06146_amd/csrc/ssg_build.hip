@@ -70,30 +70,112 @@ __device__ void wave_rank_sort(const Cand* in, Cand* out, int nc, int lane) {
   wave_sync();
 }
 
-// Greedy SSG selection over sorted candidates cs[0..nc) of node i; lane k
-// tests the candidate against kept edge k. Writes the kept ids to kid[] and
-// returns their number (<= R).
+// NB sums s[b] = sum_j (p[b]_j - c_j) (q_j - c_j), each in FP64 in index
+// order with every operation rounded on its own: the operation sequence of
+// ssgdev::dot_rel(p[b], q, c, d) for every b, the NB chains interleaved so
+// that their latencies overlap. (q_j - c_j) is formed once and shared.
+template <int NB>
+__device__ __forceinline__ void dot_rel_multi(const float* const (&p)[NB], const float* q,
+                                              const float* c, int d, double (&s)[NB]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int b = 0; b < NB; ++b) s[b] = 0.0;
+  int j = 0;
+  uintptr_t al = reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(c);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) al |= reinterpret_cast<uintptr_t>(p[b]);
+  if ((al & 15) == 0) {
+    for (; j + 4 <= d; j += 4) {
+      const float4 y = *reinterpret_cast<const float4*>(q + j);
+      const float4 z = *reinterpret_cast<const float4*>(c + j);
+      const double yz0 = (double)y.x - (double)z.x, yz1 = (double)y.y - (double)z.y;
+      const double yz2 = (double)y.z - (double)z.z, yz3 = (double)y.w - (double)z.w;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float4 x = *reinterpret_cast<const float4*>(p[b] + j);
+        s[b] = s[b] + ((double)x.x - (double)z.x) * yz0;
+        s[b] = s[b] + ((double)x.y - (double)z.y) * yz1;
+        s[b] = s[b] + ((double)x.z - (double)z.z) * yz2;
+        s[b] = s[b] + ((double)x.w - (double)z.w) * yz3;
+      }
+    }
+  }
+  for (; j < d; ++j) {
+    const double yz = (double)q[j] - (double)c[j];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) s[b] = s[b] + ((double)p[b][j] - (double)c[j]) * yz;
+  }
+}
+
+// Greedy SSG selection over sorted candidates cs[0..nc) of node i. Writes the
+// kept ids to kid[] and returns their number (<= R). Candidates are taken up
+// to SEL_NB at a time: lane k < kept computes the batch members' dot products
+// against kept edge k in interleaved chains, and the next lanes test each
+// later member against each earlier one (needed if the earlier one is kept).
+// The batch is then resolved in candidate order, member by member, with the
+// same tests and the same FP64 values as taking one candidate at a time.
+constexpr int SEL_NB = 4;
+
 __device__ int wave_select(const float* __restrict__ base, int d, int64_t i, const Cand* cs,
                            int nc, double cos2a, int R, uint32_t* kid, double* klen, int lane) {
 #pragma clang fp contract(off)
   const float* xi = base + i * d;
   int kept = 0;
-  for (int c = 0; c < nc && kept < R; ++c) {
-    const Cand cc = cs[c];
-    const float* xc = base + (int64_t)cc.id * d;
-    bool conflict = false;
-    if (lane < kept) {
-      const double dot = ssgdev::dot_rel(xc, base + (int64_t)kid[lane] * d, xi, d);
-      conflict = dot > 0.0 && dot * dot > cos2a * cc.dist * klen[lane];
+  for (int c = 0; c < nc && kept < R;) {
+    int nb = min(SEL_NB, nc - c);
+    while (nb > 1 && kept + nb * (nb - 1) / 2 > 64) --nb;  // one lane per member pair
+    const int kept0 = kept, npair = nb * (nb - 1) / 2;
+    const float* p[SEL_NB];
+    const float* q = xi;
+    int pb = -1, pa = -1;  // pair lane: member pb tested against member pa
+    if (lane < kept0) {
+      q = base + (int64_t)kid[lane] * d;
+#pragma unroll
+      for (int b = 0; b < SEL_NB; ++b) p[b] = base + (int64_t)cs[c + min(b, nb - 1)].id * d;
+    } else if (lane < kept0 + npair) {
+      int t = lane - kept0, b = 1;
+      while (t >= b) { t -= b; ++b; }  // lane kept0 + b (b - 1) / 2 + a holds pair (a, b)
+      pb = b;
+      pa = t;
+      q = base + (int64_t)cs[c + pa].id * d;
+#pragma unroll
+      for (int k = 0; k < SEL_NB; ++k) p[k] = base + (int64_t)cs[c + pb].id * d;
+    } else {
+#pragma unroll
+      for (int b = 0; b < SEL_NB; ++b) p[b] = xi;
     }
-    if (__ballot(conflict) == 0) {
-      if (lane == 0) {
-        kid[kept] = cc.id;
-        klen[kept] = cc.dist;
+    double s[SEL_NB];
+    dot_rel_multi<SEL_NB>(p, q, xi, d, s);
+    uint32_t conf = 0;  // bit b: an edge kept before the batch conflicts with member b
+#pragma unroll
+    for (int b = 0; b < SEL_NB; ++b) {
+      if (b >= nb) break;
+      const double dc = cs[c + b].dist;
+      const bool cf = lane < kept0 && s[b] > 0.0 && s[b] * s[b] > cos2a * dc * klen[lane];
+      if (__ballot(cf) != 0) conf |= 1u << b;
+    }
+    bool pcf = false;
+    if (pb >= 0) {
+      const double dc = cs[c + pb].dist, dk = cs[c + pa].dist;
+      pcf = s[0] > 0.0 && s[0] * s[0] > cos2a * dc * dk;
+    }
+    const uint64_t pmask = __ballot(pcf);
+    uint32_t acc = 0;  // bit b: member b kept
+    for (int b = 0; b < nb && kept < R; ++b) {
+      bool ok = !((conf >> b) & 1u);
+      for (int a0 = 0; a0 < b; ++a0)
+        if (((acc >> a0) & 1u) && ((pmask >> (kept0 + b * (b - 1) / 2 + a0)) & 1ull)) ok = false;
+      if (ok) {
+        acc |= 1u << b;
+        if (lane == 0) {
+          kid[kept] = cs[c + b].id;
+          klen[kept] = cs[c + b].dist;
+        }
+        ++kept;
       }
-      ++kept;
-      wave_sync();
     }
+    wave_sync();
+    c += nb;
   }
   return kept;
 }
