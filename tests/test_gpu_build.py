@@ -62,6 +62,19 @@ def test_other_angles(alpha):
     _check(base, knn, 60, 24, alpha)
 
 
+def test_degree_bound_reached():
+    """R at its bound of 64 with a 30-degree angle and 200 candidates: most
+    selections run up to 64 kept edges, past the point (58) where the
+    selection has fewer lanes left for candidate-pair tests and takes fewer
+    candidates per batch (3, 2, then 1)."""
+    cfg = synth.CONFIGS["c1"]
+    base = synth.base_vectors(cfg)[:3000]
+    knn, _ = core.knn_graph(base, 100)
+    o1, o2 = _check(base, knn, 200, 64, 30.0)
+    assert ((o1 != core.SENT).sum(1) >= 60).mean() > 0.5
+    assert ((o2 != core.SENT).sum(1) >= 60).mean() > 0.5
+
+
 def test_large_candidate_sets_and_duplicates():
     """l + Kk above 256 (the larger LDS layout), exact duplicate points
     (distance-0 candidates dropped), ragged n."""
