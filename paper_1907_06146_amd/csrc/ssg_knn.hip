@@ -83,11 +83,6 @@ __device__ __forceinline__ float bf16_f32(uint16_t h) { return __uint_as_float((
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
-  uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-  return ((uint64_t)hi << 32) | lo;
-}
 // Global-memory views of workspace pointers. The pointers reach the kernels
 // inside argument structs, so the compiler cannot tell their address space
 // and would emit flat accesses, which count against the LDS wait counter as
@@ -329,8 +324,15 @@ __device__ void merge_queue(SM& sm, uint64_t* lists, int KP, int64_t r0) {
         const uint64_t v = sm.mg.q2[off + c0 + lane];
         nk = (v & 0xFFFFFFFF00000000ull) | (v & 0x1FFFFFFull);
       }
+      // rank among the new keys: the keys are broadcast from LDS (Ok is
+      // free until the scatter below), several reads in flight at a time
+      // (a readlane per key costs more: each result passes through SGPRs)
+      if ((uint32_t)lane < m) Ok[lane] = nk;
+      wave_sync();
       uint32_t r1 = 0;
-      for (uint32_t j = 0; j < m; ++j) r1 += readlane64(nk, j) < nk;
+#pragma unroll 4
+      for (uint32_t j = 0; j < m; ++j) r1 += Ok[j] < nk;
+      wave_sync();
       if ((uint32_t)lane < m) Nk[r1] = nk;
       wave_sync();
       if ((uint32_t)lane < m) {
